@@ -1,0 +1,47 @@
+"""FP64 CPU oracle for Newton-Chebyshev preconditioned CG.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are its only users.  The GPU library never imports it.
+"""
+
+from .nc import (
+    ChebScalars,
+    CountingOperator,
+    NCResult,
+    NotSPD,
+    PCGResult,
+    chebyshev_apply,
+    chebyshev_scalars,
+    cluster_indicator,
+    csr,
+    hotelling_step,
+    jacobi_scale,
+    lanczos_extremes,
+    nc_apply_unscaled,
+    nc_pcg,
+    newton_apply,
+    newton_zetas,
+    pcg,
+    preconditioned_spectrum,
+)
+
+__all__ = [
+    "ChebScalars",
+    "CountingOperator",
+    "NCResult",
+    "NotSPD",
+    "PCGResult",
+    "chebyshev_apply",
+    "chebyshev_scalars",
+    "cluster_indicator",
+    "csr",
+    "hotelling_step",
+    "jacobi_scale",
+    "lanczos_extremes",
+    "nc_apply_unscaled",
+    "nc_pcg",
+    "newton_apply",
+    "newton_zetas",
+    "pcg",
+    "preconditioned_spectrum",
+]

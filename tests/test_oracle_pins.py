@@ -1,0 +1,66 @@
+"""The FP64 oracle against what the paper and mathematics fix (CPU only)."""
+
+import pytest
+
+import pins
+
+
+def test_rho_matches_chebyshev_ratio():
+    pins.check_rho_closed_form()
+
+
+def test_newton_zetas_match_theorem2_closed_form():
+    pins.check_zeta_closed_form()
+
+
+def test_apply_on_diagonal_matches_closed_form_polynomial():
+    pins.check_poly_closed_form()
+
+
+def test_equioscillation_bound():
+    pins.check_equioscillation()
+
+
+def test_newton_recursion_equals_chebyshev_recurrence():
+    pins.check_newton_equals_chebyshev()
+
+
+def test_hotelling_error_squares():
+    pins.check_hotelling()
+
+
+def test_table1_eigen_statistics_exact():
+    pins.check_table1_spectrum()
+
+
+def test_table1_iteration_counts_soft():
+    pins.check_table1_iterations()
+
+
+def test_pcg_matches_dense_solve():
+    pins.check_dense_solve()
+
+
+def test_pcg_finite_termination():
+    pins.check_finite_termination()
+
+
+def test_flexible_beta_keeps_directions_conjugate():
+    pins.check_flexible_local_orthogonality()
+
+
+def test_table3_counting_identities():
+    pins.check_counting_identities()
+
+
+def test_lanczos_exact_when_space_spanned():
+    pins.check_lanczos_exact_small()
+
+
+def test_underestimated_bound_breaks_down():
+    pins.check_indefinite_breakdown()
+
+
+@pytest.mark.slow
+def test_table3_lap1600_iterations_soft():
+    pins.check_table3_lap1600()
