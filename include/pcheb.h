@@ -1,0 +1,211 @@
+/*
+ * pcheb — Newton-Chebyshev polynomial-preconditioned conjugate gradients on
+ * AMD MI355X (gfx950).
+ *
+ * The preconditioner is the degree-k polynomial p_k(A) that solves the
+ * Chebyshev min-max problem on an interval [alpha, beta] enclosing the spectrum
+ * of the Jacobi-scaled operator A = D^-1/2 A_hat D^-1/2 (Bergamaschi &
+ * Martinez, arXiv:2008.01440, Sec. 3, eqs. maxmin and cheb).  It is applied
+ * with k operator products by the three-term recurrence of Alg. 2, and
+ * equals the Newton-based preconditioner of Alg. 1 (Theorem 2).  The
+ * "modified parameter" of Sec. 4 multiplies theta = (alpha + beta)/2 by a
+ * scale s >= 1 with delta = (beta - alpha)/2 unchanged.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named in the argument documentation as "device" must point to
+ *    memory on the current HIP device; "host" pointers to host memory.
+ *  - Vectors are float64, length n, unit stride.  Several right-hand sides
+ *    are stored one after another with leading dimension ld >= n.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL means the null
+ *    stream) and is ordered with the caller's other work on that stream.
+ *  - No C++ exception crosses this interface.  Every call returns a
+ *    pcheb_status; on failure pcheb_last_error() describes the cause.
+ *  - A handle may be used by one host thread at a time; distinct handles are
+ *    independent.
+ */
+#ifndef PCHEB_H
+#define PCHEB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pcheb_status {
+  PCHEB_OK = 0,
+  PCHEB_INVALID = 1,        /* an argument is out of range or inconsistent */
+  PCHEB_NOT_SPD = 2,        /* the operator has a non-positive diagonal entry */
+  PCHEB_OOM = 3,            /* a device allocation failed */
+  PCHEB_HIP = 4,            /* a HIP runtime call failed */
+  PCHEB_NOT_CONVERGED = 5,  /* maxit iterations ran without reaching tol */
+  PCHEB_BREAKDOWN = 6,      /* (p, Ap) <= 0, (r, z) <= 0, or a non-finite value */
+  PCHEB_BUDGET = 7,         /* serving: a request needs more memory than the budget */
+  PCHEB_NOT_FOUND = 8,      /* serving: unknown request id */
+  PCHEB_PENDING = 9         /* serving: the request has not finished */
+} pcheb_status;
+
+typedef enum pcheb_op_kind {
+  PCHEB_OP_CSR = 0,         /* general sparse matrix in CSR form */
+  PCHEB_OP_SELL = 1,        /* CSR input, stored and streamed as SELL-C-sigma */
+  PCHEB_OP_STENCIL7 = 2,    /* matrix-free 7-point Dirichlet Laplacian (diagonal 6, neighbours -1) */
+  PCHEB_OP_STENCIL27H = 3   /* matrix-free 27-point harmonic-mean diffusion on cell coefficients */
+} pcheb_op_kind;
+
+typedef enum pcheb_precision {
+  PCHEB_F64 = 0,            /* p_k(A) recurrence in float64 */
+  PCHEB_F32 = 1,            /* matrix values and iterates stored and accumulated in float32 */
+  PCHEB_BF16 = 2            /* matrix values and iterates stored in bfloat16, accumulated in float32 */
+} pcheb_precision;
+
+/*
+ * The unscaled SPD operator A_hat.
+ *
+ * CSR / SELL: rowptr (int32[n+1]), colind (int32[nnz]) and values
+ *   (float64[nnz]) are device arrays in CSR form with nnz < 2^31; they are
+ *   borrowed and must stay valid and unchanged until pcheb_destroy.
+ *   sell_C must be 0 or 64 (rows per chunk; one wavefront per chunk) and
+ *   sell_sigma >= 1 is the row-sorting window (1 keeps the row order).
+ * STENCIL7: the 7-point Laplacian on an nx*ny*nz grid, x fastest, with
+ *   homogeneous Dirichlet boundaries; n must equal nx*ny*nz.
+ * STENCIL27H: cell-centred diffusion on an nx*ny*nz grid, x fastest.
+ *   cell_coeff (float64[n], device, borrowed, all > 0) holds the cell
+ *   coefficients k_i.  Cell i couples to each of its 26 neighbours j with
+ *   -H(k_i, k_j), H(a, b) = 2ab/(a + b); a neighbour outside the grid adds
+ *   k_i to the diagonal (zero-Dirichlet ghost cell).
+ */
+typedef struct pcheb_operator {
+  int32_t kind;             /* pcheb_op_kind */
+  int64_t n;                /* number of unknowns */
+  const int32_t* rowptr;    /* CSR/SELL */
+  const int32_t* colind;    /* CSR/SELL */
+  const double* values;     /* CSR/SELL */
+  int64_t nnz;              /* CSR/SELL */
+  int32_t nx, ny, nz;       /* stencils */
+  const double* cell_coeff; /* STENCIL27H */
+  int32_t sell_C;           /* SELL */
+  int32_t sell_sigma;       /* SELL */
+} pcheb_operator;
+
+/*
+ * Preconditioner parameters.  lambda_min < lambda_max bound the spectrum of
+ * the Jacobi-scaled operator D^-1/2 A_hat D^-1/2 (Sec. 5 scales every matrix
+ * first); lambda_max below the true largest eigenvalue makes p_k(A) A
+ * indefinite for odd k.  theta_scale is the modified parameter s of Sec. 4
+ * (1 gives the min-max optimal polynomial; the paper uses 1.01 and 1.001).
+ * fuse_steps > 1 asks the matrix-free stencil paths to run that many
+ * recurrence steps per pass over memory (ignored elsewhere; 0 or 1 = off).
+ */
+typedef struct pcheb_params {
+  int32_t k;                /* degree = operator products per application, 0 <= k <= 1000 */
+  double lambda_min;
+  double lambda_max;
+  double theta_scale;       /* s >= 1 */
+  int32_t prec;             /* pcheb_precision */
+  int32_t fuse_steps;
+} pcheb_params;
+
+/* Flags of pcg_solve. */
+#define PCG_FLEXIBLE     0x1u  /* Polak-Ribiere beta (z_new, r_new - r_old)/(r_old, z_old) */
+#define PCG_X0_GIVEN     0x2u  /* x holds the initial guess; otherwise x0 = 0 */
+#define PCG_TIME_KERNELS 0x4u  /* time the middle recurrence steps with HIP events */
+#define PCG_NO_GRAPH     0x8u  /* launch each kernel directly instead of replaying HIP graphs */
+#define PCG_REFRESH      0x10u /* replace r by b - A x every 50 iterations */
+
+typedef struct pcg_stats {
+  int32_t iters;            /* PCG iterations (operator products q = A p) */
+  int32_t converged;        /* 1 if recursive ||r|| / ||b|| < tol */
+  int32_t status;           /* pcheb_status of the solve */
+  int32_t pad0;
+  double relres;            /* recursive residual of the scaled system at exit */
+  double relres_true;       /* ||b - A x|| / ||b|| of the scaled system, recomputed at exit */
+  double relres_true_hat;   /* ||b_hat - A_hat x_hat|| / ||b_hat||, unscaled */
+  int64_t n_spmv;           /* operator products, preconditioner included */
+  int64_t n_dot;            /* scalar products, counted as in Table 3 of the paper */
+  double seconds;           /* host wall time of the call */
+  double step_ms;           /* PCG_TIME_KERNELS: summed time of the timed middle steps */
+  int64_t step_launches;    /* PCG_TIME_KERNELS: number of middle-step launches timed */
+} pcg_stats;
+
+typedef struct pcheb_handle_s* pcheb_handle;
+
+/*
+ * Build the preconditioner for A_hat (Sec. 3 coefficients, Sec. 4 scaling):
+ * computes the diagonal, the recurrence scalars theta' = s (lambda_min +
+ * lambda_max)/2, delta = (lambda_max - lambda_min)/2, sigma = theta'/delta,
+ * rho_0 = 1/sigma, rho_j = 1/(2 sigma - rho_{j-1}) (eq. rhocheb), the
+ * reduced-precision and SELL copies the library owns, and the workspace for
+ * one right-hand side.  Synchronises `stream` once.
+ * Errors: INVALID (k out of range, lambda_min <= 0, lambda_min >= lambda_max,
+ * s < 1, null or inconsistent arrays, unsupported SELL chunk), NOT_SPD
+ * (diagonal <= 0 or a coefficient <= 0), OOM, HIP.  *out is set only on OK.
+ */
+pcheb_status pcheb_setup(const pcheb_operator* A, const pcheb_params* p, hipStream_t stream,
+                         pcheb_handle* out);
+
+/*
+ * z = D^-1/2 p_k(A) D^-1/2 r = p_k(D^-1 A_hat) D^-1 r: the preconditioner for
+ * the unscaled system, by Alg. 2 (step j uses rho_j and rho_{j-1}, matching
+ * the p_k recurrence of Sec. 3).  r and z are device float64 arrays of
+ * nrhs vectors with leading dimension ld; z must not overlap r.  Enqueued on
+ * `stream` without host synchronisation.  Errors: INVALID, HIP, OOM.
+ */
+pcheb_status pcheb_apply(pcheb_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
+                         hipStream_t stream);
+
+/*
+ * y = A_hat x in float64 (the unscaled operator; used by the solver for
+ * q = A p and by callers to check residuals).  Device arrays, nrhs vectors
+ * with leading dimension ld, y must not overlap x.  Errors: INVALID, HIP.
+ */
+pcheb_status pcheb_matvec(pcheb_handle h, const double* x, double* y, int32_t nrhs, int64_t ld,
+                          hipStream_t stream);
+
+/*
+ * Solve A_hat x = b by PCG preconditioned with pcheb_apply.  This is PCG on
+ * the Jacobi-scaled system of Sec. 5 written in unscaled variables: the
+ * iterates are x_hat = D^-1/2 x and the stop test ||r|| / ||b|| < tol uses
+ * the D^-1-weighted norm, which is the scaled system's Euclidean norm.
+ * b (read) and x (written; read first if PCG_X0_GIVEN) are device float64
+ * arrays of nrhs vectors with leading dimension ld.  The outer iteration
+ * (residual update, alpha/beta dot products) is float64 whatever the
+ * preconditioner precision.  Scalars stay on the device; the host reads
+ * them once per group of iterations and at exit, and `stream` is
+ * synchronised on return.  stats (host, may be NULL) receives per-solve
+ * statistics (nrhs > 1: the slowest right-hand side).
+ * Returns OK, NOT_CONVERGED (x holds the last iterate), BREAKDOWN, INVALID,
+ * HIP or OOM.
+ */
+pcheb_status pcg_solve(pcheb_handle h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                       double tol, int32_t maxit, uint32_t flags, pcg_stats* stats,
+                       hipStream_t stream);
+
+/* Release everything the handle owns (not the borrowed operator arrays).  NULL is allowed. */
+pcheb_status pcheb_destroy(pcheb_handle h);
+
+/* Description of the last failure on the calling thread ("" if none).  Valid until the next call. */
+const char* pcheb_last_error(void);
+
+/* Device bytes pcheb_setup plus pcg_solve with nrhs right-hand sides will allocate. */
+size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs);
+
+/*
+ * Extreme Ritz values of nsteps Lanczos steps (full reorthogonalisation) on
+ * the Jacobi-scaled operator D^-1/2 A_hat D^-1/2, started from v0 (device
+ * float64[n], need not be normalised).  The paper estimates the bounds by
+ * the power method and DACG (Sec. 5.1); callers widen lambda_max by a
+ * safety factor before pcheb_setup.  Writes *lambda_min, *lambda_max (host).
+ * Allocates nsteps + 1 vectors of workspace for the duration of the call.
+ * Errors: INVALID, NOT_SPD, OOM, HIP.
+ */
+pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
+                                   double* lambda_min, double* lambda_max, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCHEB_H */

@@ -1,0 +1,268 @@
+"""ctypes declarations of include/pcheb.h and argument-marshalling wrappers."""
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libpcheb.so"
+
+STATUS = {
+    0: "OK",
+    1: "INVALID",
+    2: "NOT_SPD",
+    3: "OOM",
+    4: "HIP",
+    5: "NOT_CONVERGED",
+    6: "BREAKDOWN",
+    7: "BUDGET",
+    8: "NOT_FOUND",
+    9: "PENDING",
+}
+
+OP_KIND = {"csr": 0, "sell": 1, "stencil7": 2, "stencil27h": 3}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+
+PCG_FLEXIBLE = 0x1
+PCG_X0_GIVEN = 0x2
+PCG_TIME_KERNELS = 0x4
+PCG_NO_GRAPH = 0x8
+PCG_REFRESH = 0x10
+
+
+class PchebError(RuntimeError):
+    """A pcheb call returned a status other than OK (or an expected one)."""
+
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class COperator(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("rowptr", ctypes.c_void_p),
+        ("colind", ctypes.c_void_p),
+        ("values", ctypes.c_void_p),
+        ("nnz", ctypes.c_int64),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("cell_coeff", ctypes.c_void_p),
+        ("sell_C", ctypes.c_int32),
+        ("sell_sigma", ctypes.c_int32),
+    ]
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("lambda_min", ctypes.c_double),
+        ("lambda_max", ctypes.c_double),
+        ("theta_scale", ctypes.c_double),
+        ("prec", ctypes.c_int32),
+        ("fuse_steps", ctypes.c_int32),
+    ]
+
+
+class CStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("relres", ctypes.c_double),
+        ("relres_true", ctypes.c_double),
+        ("relres_true_hat", ctypes.c_double),
+        ("n_spmv", ctypes.c_int64),
+        ("n_dot", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+        ("step_ms", ctypes.c_double),
+        ("step_launches", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_PKG, _LIB_NAME)
+
+
+def load_library():
+    """Load libpcheb.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2008_01440_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    lib.pcheb_setup.argtypes = [ctypes.POINTER(COperator), ctypes.POINTER(CParams), vp, ctypes.POINTER(vp)]
+    lib.pcheb_apply.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.pcheb_matvec.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.pcg_solve.argtypes = [vp, vp, vp, i32, i64, f64, i32, u32, ctypes.POINTER(CStats), vp]
+    lib.pcheb_destroy.argtypes = [vp]
+    lib.pcheb_last_error.argtypes = []
+    lib.pcheb_last_error.restype = ctypes.c_char_p
+    lib.pcheb_footprint_bytes.argtypes = [ctypes.POINTER(COperator), ctypes.POINTER(CParams), i32]
+    lib.pcheb_footprint_bytes.restype = ctypes.c_size_t
+    lib.pcheb_estimate_bounds.argtypes = [ctypes.POINTER(COperator), vp, i32, ctypes.POINTER(f64),
+                                          ctypes.POINTER(f64), vp]
+    for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
+                 "pcheb_estimate_bounds"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def pcheb_last_error() -> str:
+    return load_library().pcheb_last_error().decode()
+
+
+def _check(status, allowed=(0,)):
+    if status not in allowed:
+        raise PchebError(status, pcheb_last_error())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, dtype_name):
+    """Device pointer of a contiguous CUDA tensor with the expected dtype."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (CUDA/HIP) tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise ValueError(f"expected dtype {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """The unscaled SPD operator A_hat; keeps the tensors it borrows alive."""
+
+    def __init__(self, c: COperator, keep=()):
+        self.c = c
+        self._keep = tuple(keep)
+
+    @property
+    def n(self) -> int:
+        return int(self.c.n)
+
+    @staticmethod
+    def stencil7(nx: int, ny: int = None, nz: int = None) -> "Operator":
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        c = COperator(kind=OP_KIND["stencil7"], n=nx * ny * nz, nx=nx, ny=ny, nz=nz)
+        return Operator(c)
+
+    @staticmethod
+    def stencil27h(kappa) -> "Operator":
+        """kappa: float64 device tensor of shape (nz, ny, nx) (x fastest)."""
+        nz, ny, nx = kappa.shape
+        c = COperator(kind=OP_KIND["stencil27h"], n=nx * ny * nz, nx=nx, ny=ny, nz=nz,
+                      cell_coeff=_dptr(kappa, "float64"))
+        return Operator(c, (kappa,))
+
+    @staticmethod
+    def csr(rowptr, colind, values, sell: bool = False, sigma: int = 1) -> "Operator":
+        """CSR device tensors (int32, int32, float64); sell=True streams it as SELL-C-sigma."""
+        n = rowptr.numel() - 1
+        c = COperator(kind=OP_KIND["sell" if sell else "csr"], n=n, rowptr=_dptr(rowptr, "int32"),
+                      colind=_dptr(colind, "int32"), values=_dptr(values, "float64"), nnz=values.numel(),
+                      sell_C=64 if sell else 0, sell_sigma=sigma)
+        return Operator(c, (rowptr, colind, values))
+
+
+class Handle:
+    """An owned pcheb_handle (release with pcheb_destroy or as a context manager)."""
+
+    def __init__(self, ptr, op: Operator, params: CParams):
+        self.ptr = ptr
+        self.op = op
+        self.params = params
+
+    @property
+    def n(self):
+        return self.op.n
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        pcheb_destroy(self)
+
+
+def _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps):
+    return CParams(k=k, lambda_min=lambda_min, lambda_max=lambda_max, theta_scale=theta_scale,
+                   prec=PREC[prec] if isinstance(prec, str) else int(prec), fuse_steps=fuse_steps)
+
+
+def pcheb_setup(op: Operator, k: int, lambda_min: float, lambda_max: float, theta_scale: float = 1.001,
+                prec: str = "f64", fuse_steps: int = 1, stream=None) -> Handle:
+    lib = load_library()
+    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps)
+    out = ctypes.c_void_p()
+    _check(lib.pcheb_setup(ctypes.byref(op.c), ctypes.byref(p), _stream(stream), ctypes.byref(out)))
+    return Handle(out, op, p)
+
+
+def pcheb_apply(h: Handle, r, z, stream=None):
+    nrhs = 1 if r.dim() == 1 else r.shape[0]
+    _check(load_library().pcheb_apply(h.ptr, _dptr(r, "float64"), _dptr(z, "float64"), nrhs, h.n, _stream(stream)))
+
+
+def pcheb_matvec(h: Handle, x, y, stream=None):
+    nrhs = 1 if x.dim() == 1 else x.shape[0]
+    _check(load_library().pcheb_matvec(h.ptr, _dptr(x, "float64"), _dptr(y, "float64"), nrhs, h.n,
+                                        _stream(stream)))
+
+
+def pcg_solve(h: Handle, b, x, tol: float = 1e-8, maxit: int = 100000, flexible: bool = False,
+              x0_given: bool = False, time_kernels: bool = False, graph: bool = True, refresh: bool = False,
+              stream=None, check: bool = True) -> dict:
+    """Returns the statistics as a dict (status name under 'status').  With check=True,
+    BREAKDOWN and errors raise; NOT_CONVERGED is reported in the dict."""
+    flags = ((PCG_FLEXIBLE if flexible else 0) | (PCG_X0_GIVEN if x0_given else 0)
+             | (PCG_TIME_KERNELS if time_kernels else 0) | (0 if graph else PCG_NO_GRAPH)
+             | (PCG_REFRESH if refresh else 0))
+    st = CStats()
+    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    status = load_library().pcg_solve(h.ptr, _dptr(b, "float64"), _dptr(x, "float64"), nrhs, h.n, tol, maxit,
+                                      flags, ctypes.byref(st), _stream(stream))
+    if check:
+        _check(status, allowed=(0, 5))
+    out = {name: getattr(st, name) for name, _ in CStats._fields_ if name != "pad0"}
+    out["status"] = STATUS.get(status, str(status))
+    return out
+
+
+def pcheb_destroy(h: Handle):
+    if h.ptr:
+        _check(load_library().pcheb_destroy(h.ptr))
+        h.ptr = None
+
+
+def pcheb_footprint_bytes(op: Operator, k: int, lambda_min: float = 0.1, lambda_max: float = 2.0,
+                          theta_scale: float = 1.001, prec: str = "f64", nrhs: int = 1) -> int:
+    p = _params(k, lambda_min, lambda_max, theta_scale, prec, 1)
+    return int(load_library().pcheb_footprint_bytes(ctypes.byref(op.c), ctypes.byref(p), nrhs))
+
+
+def pcheb_estimate_bounds(op: Operator, v0, nsteps: int = 30, stream=None):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().pcheb_estimate_bounds(ctypes.byref(op.c), _dptr(v0, "float64"), nsteps,
+                                                ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
+    return lo.value, hi.value

@@ -1,0 +1,184 @@
+// Device-side building blocks shared by every kernel of the library:
+// storage types (float64 / float32 / bfloat16 with float32 arithmetic),
+// wavefront and block sums, the single-pass grid reduction, XCD-aware tile
+// enumeration and the solver state that lives in device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcheb {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per block for every kernel
+constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kMaxGrid = 8192;     // cap on blocks of grid-stride kernels (bounds reduction partials)
+constexpr int kMaxReduce = 4;      // values reduced per kernel at most
+
+// ---------------------------------------------------------------- storage types
+
+struct bf16 {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+// float -> bfloat16, round to nearest, ties to even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t float_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+template <class T>
+struct Store;
+
+template <>
+struct Store<double> {
+  using acc = double;
+  static __device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(double* p, int64_t i, double v) { p[i] = v; }
+};
+
+template <>
+struct Store<float> {
+  using acc = float;
+  static __device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(float* p, int64_t i, float v) { p[i] = v; }
+};
+
+template <>
+struct Store<bf16> {
+  using acc = float;
+  static __device__ __forceinline__ float ld(const bf16* p, int64_t i) { return bf16_to_float(p[i].bits); }
+  static __device__ __forceinline__ void st(bf16* p, int64_t i, float v) { p[i].bits = float_to_bf16(v); }
+};
+
+// ---------------------------------------------------------------- solver state
+
+// Scalars of one PCG solve.  They stay in device memory: kernels read alpha
+// and beta from here and the last block of each reduction writes them, so the
+// host never sits between two iterations.
+struct DevState {
+  double gamma;      // (r, z) for the current z
+  double alpha;      // gamma / (p, q)
+  double beta;       // direction update coefficient
+  double pq;         // (p, A p)
+  double rr;         // ||r||^2 in the D^-1 weighted norm
+  double bb;         // ||b||^2 in the D^-1 weighted norm
+  double tol;        // relative tolerance
+  double relres;     // sqrt(rr / bb)
+  double true_rr;    // ||b - A x||^2, D^-1 weighted (exit check)
+  double true_rr_hat;// ||b - A x||^2, unweighted
+  double bb_hat;     // ||b||^2, unweighted
+  double scratch;    // result slot of stand-alone reductions
+  int32_t iter;      // completed iterations
+  int32_t maxit;
+  int32_t done;      // 0 running, 1 converged, 2 breakdown, 3 iteration limit
+  int32_t flexible;  // 1: Polak-Ribiere beta
+  int32_t refreshes; // true-residual replacements performed
+  int32_t pad;
+};
+
+enum : int32_t { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIter = 3 };
+
+// Partial sums of a grid reduction: one slot of kMaxReduce doubles per block
+// plus an arrival counter that the last block resets to zero.
+struct ReduceBuf {
+  double* partials;
+  unsigned int* counter;
+};
+
+// ---------------------------------------------------------------- reductions
+
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, kWave);
+  }
+}
+
+// Sum over the block; the result is valid in thread 0 only.  Fixed order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
+  __shared__ double sh[kBlock / kWave][NV > 0 ? NV : 1];
+  wave_sum<NV>(v);
+  const int lane = tid % kWave, wave = tid / kWave;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = sh[0][i];
+      for (int w = 1; w < kBlock / kWave; ++w) s += sh[w][i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double load_l2(const double* p) {
+  // read past the per-CU vector cache: partial sums were written by other CUs
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Single-pass grid reduction.  Every block sums its values and stores them in
+// its own slot; the block that arrives last adds all slots in slot order (a
+// fixed order, so the result is reproducible for a given grid) and calls
+// fin(total) from thread 0.  All threads of every block must call it.
+template <int NV, class Fin>
+__device__ __forceinline__ void grid_reduce(double (&v)[NV], ReduceBuf rb, Fin fin) {
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const unsigned nb = gridDim.x;
+  __shared__ unsigned int is_last;
+  block_sum<NV>(v, tid);
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) rb.partials[size_t(blockIdx.x) * kMaxReduce + i] = v[i];
+    __threadfence();
+    const unsigned int ticket = atomicAdd(rb.counter, 1u);
+    is_last = (ticket == nb - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (unsigned b = tid; b < nb; b += kBlock) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += load_l2(rb.partials + size_t(b) * kMaxReduce + i);
+  }
+  block_sum<NV>(acc, tid);
+  if (tid == 0) {
+    *rb.counter = 0u;
+    fin(acc);
+  }
+}
+
+// ---------------------------------------------------------------- tile enumeration
+
+// Blocks are dispatched to the XCDs round robin (block b runs on XCD b % 8).
+// Give every XCD one contiguous range of tiles, so the halo that neighbouring
+// tiles share is reused in that XCD's L2.  The grid size must be a multiple of 8.
+struct XcdTiles {
+  uint32_t begin, end, step;
+  __device__ __forceinline__ explicit XcdTiles(uint32_t ntiles) {
+    const uint32_t xcd = blockIdx.x % kNumXcd;
+    const uint32_t local = blockIdx.x / kNumXcd;
+    const uint32_t per = (ntiles + kNumXcd - 1) / kNumXcd;
+    const uint32_t lo = xcd * per;
+    const uint32_t hi = lo + per < ntiles ? lo + per : ntiles;
+    begin = lo + local;
+    end = hi;
+    step = gridDim.x / kNumXcd;
+  }
+};
+
+}  // namespace pcheb

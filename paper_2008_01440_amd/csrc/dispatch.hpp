@@ -1,0 +1,96 @@
+// Launch an operator kernel for the handle's operator kind with a given
+// input functor and epilogue.  SCALED selects M = D^-1 A_hat (the
+// preconditioner recurrence) instead of A_hat (the outer iteration).
+#pragma once
+
+#include "epilogues.hpp"
+#include "handle.hpp"
+#include "operators.hpp"
+
+namespace pcheb {
+
+constexpr int kZChunk = 8;  // planes marched per stencil tile
+
+struct StencilGrid {
+  uint32_t tiles_x, tiles_y, ntiles, grid;
+};
+
+inline StencilGrid stencil_grid(const pcheb_operator& op) {
+  StencilGrid g;
+  g.tiles_x = uint32_t((op.nx + 63) / 64);
+  g.tiles_y = uint32_t((op.ny + 3) / 4);
+  const uint32_t tz = uint32_t((op.nz + kZChunk - 1) / kZChunk);
+  g.ntiles = g.tiles_x * g.tiles_y * tz;
+  g.grid = round_grid(g.ntiles);
+  return g;
+}
+
+// Tv: value type of CSR/SELL arrays (float64 for A_hat; storage type for D^-1 A_hat).
+template <bool SCALED, class Tv, class In, class Epi>
+void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Epi epi, hipStream_t s) {
+  using acc = typename Epi::acc;
+  const pcheb_operator& op = h.op;
+  switch (op.kind) {
+    case PCHEB_OP_STENCIL7: {
+      const StencilGrid g = stencil_grid(op);
+      k_stencil7<SCALED, kZChunk, In, Epi><<<g.grid, dim3(64, 4), 0, s>>>(in, epi, op.nx, op.ny, op.nz, g.tiles_x,
+                                                                        g.tiles_y, g.ntiles, h.rb());
+      break;
+    }
+    case PCHEB_OP_STENCIL27H: {
+      const StencilGrid g = stencil_grid(op);
+      const acc* kappa = nullptr;
+      if constexpr (sizeof(acc) == 8) {
+        kappa = reinterpret_cast<const acc*>(op.cell_coeff);
+      } else {
+        kappa = reinterpret_cast<const acc*>(h.kappa_lo);
+      }
+      k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<g.grid, dim3(64, 4), 0, s>>>(
+          in, epi, kappa, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb());
+      break;
+    }
+    case PCHEB_OP_CSR: {
+      const int rows = kBlock / h.lanes;
+      const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);
+      const uint32_t grid = round_grid(tiles);
+#define PCHEB_CSR_CASE(L)                                                                              \
+  case L:                                                                                              \
+    k_csr<L, Tv, In, Epi><<<grid, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n, uint32_t(tiles), \
+                                                 h.rb());                                              \
+    break;
+      switch (h.lanes) {
+        PCHEB_CSR_CASE(4)
+        PCHEB_CSR_CASE(8)
+        PCHEB_CSR_CASE(16)
+        PCHEB_CSR_CASE(32)
+        default:
+          PCHEB_CSR_CASE(64)
+      }
+#undef PCHEB_CSR_CASE
+      break;
+    }
+    case PCHEB_OP_SELL: {
+      const uint64_t tiles = uint64_t((h.nchunks + 3) / 4);
+      const uint32_t grid = round_grid(tiles);
+      k_sell<Tv, In, Epi><<<grid, kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val, h.sell_perm, in, epi,
+                                                  h.n, uint32_t(tiles), h.rb());
+      break;
+    }
+    default:
+      fail(PCHEB_INVALID, "unknown operator kind");
+  }
+}
+
+// A_hat applied to a float64 input functor (the outer iteration and residuals).
+template <class In, class Epi>
+void launch_ahat(const Handle& h, In in, Epi epi, hipStream_t s) {
+  launch_op<false, double>(h, h.op.values, h.sell_aval, in, epi, s);
+}
+
+// D^-1 A_hat applied to an input in the storage precision T.
+template <class T, class In, class Epi>
+void launch_bop(const Handle& h, In in, Epi epi, hipStream_t s) {
+  launch_op<true, T>(h, reinterpret_cast<const T*>(h.csr_bval), reinterpret_cast<const T*>(h.sell_bval), in, epi, s);
+}
+
+}  // namespace pcheb

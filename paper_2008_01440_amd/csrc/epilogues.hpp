@@ -1,0 +1,200 @@
+// Per-row arithmetic run by the operator kernels (see operators.hpp).
+//
+// The preconditioner recurrence runs on B = D^-1 A_hat with input
+// s = D^-1 r, which is the similarity transform of Alg. 2 on the scaled
+// matrix A = D^-1/2 A_hat D^-1/2:  D^-1/2 p_k(A) D^-1/2 = p_k(B) D^-1.
+// With y_0 = s / theta', step j (1 <= j <= k) of the recurrence is
+//     y_j = rho_j (2 sigma y_{j-1} - rho_{j-1} y_{j-2} + (2/delta)(s - B y_{j-1}))
+//         = a_j y_{j-1} - b_j y_{j-2} + c_j (s - B y_{j-1}),
+// with a_j = 2 sigma rho_j, b_j = rho_j rho_{j-1} (and y_{-1} = 0, so step 1
+// drops that term), c_j = 2 rho_j / delta.  Step 1 then equals
+// (2 rho_1/delta)(2 s - B s/theta'), the first line of Alg. 2.
+#pragma once
+
+#include "common.hpp"
+
+namespace pcheb {
+
+// D^-1 of the unscaled operator: a stored array or a constant (7-point stencil).
+struct InvDiag {
+  const double* p;
+  double c;
+  __device__ __forceinline__ double operator()(int64_t i) const { return p ? p[i] : c; }
+};
+
+// Middle (and first) steps: y_j in the storage precision T.
+template <class T, bool FIRST>
+struct EpiChebStep {
+  using acc = typename Store<T>::acc;
+  static constexpr int NV = 1;
+  static constexpr bool reduce = false;
+  const T* yprev;  // y_{j-2}; unused when FIRST
+  const T* s;      // D^-1 r in storage precision
+  T* out;          // y_j
+  acc a, b, c;
+  DevState* st;
+  const DevState* guard;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, double (&)[NV]) const {
+    acc v = a * y + c * (Store<T>::ld(s, i) - by);
+    if (!FIRST) v -= b * Store<T>::ld(yprev, i);
+    Store<T>::st(out, i, v);
+  }
+  __device__ void fin(double (&)[NV]) const {}
+};
+
+// Last step: z = y_k in float64 and, inside a solve, the partial sums of
+// (r, z) and (z, q).  The last block then forms, on the device,
+//   gamma_new = (r, z);
+//   beta = gamma_new / gamma                     (Fletcher-Reeves), or
+//   beta = (z, r - r_old) / gamma = -(z, q)/(p, q) (Polak-Ribiere; r - r_old = -alpha q
+//          and gamma = alpha (p, q)),
+// and flags a breakdown if gamma_new <= 0 (indefinite preconditioner).
+// `init` marks the application before the first iteration: gamma only.
+template <class T, bool FIRST, bool DOTS>
+struct EpiChebLast {
+  using acc = typename Store<T>::acc;
+  static constexpr int NV = 2;
+  static constexpr bool reduce = DOTS;
+  const T* yprev;
+  const T* s;
+  double* z;
+  const double* r;  // float64 residual (for the dot products)
+  const double* q;  // A p of this iteration (flexible beta only)
+  acc a, b, c;
+  DevState* st;
+  const DevState* guard;
+  int init;
+  int flexible;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, double (&part)[NV]) const {
+    acc v = a * y + c * (Store<T>::ld(s, i) - by);
+    if (!FIRST) v -= b * Store<T>::ld(yprev, i);
+    const double zi = double(v);
+    z[i] = zi;
+    if (DOTS) {
+      part[0] += r[i] * zi;
+      if (flexible) part[1] += zi * q[i];
+    }
+  }
+  __device__ void fin(double (&t)[NV]) const { finish_beta(st, t[0], t[1], init, flexible); }
+
+  static __device__ void finish_beta(DevState* st, double rz, double zq, int init, int flexible) {
+    if (!(rz > 0.0) || !isfinite(rz)) {
+      st->done = kBreakdown;
+      return;
+    }
+    if (init) {
+      st->beta = 0.0;
+    } else if (flexible) {
+      st->beta = -zq / st->pq;
+    } else {
+      st->beta = rz / st->gamma;
+    }
+    st->gamma = rz;
+  }
+};
+
+// q = A p where the input functor forms p = z + beta p_old; stores p and q and
+// reduces (p, q).  The last block sets alpha = gamma / (p, q) or flags a
+// breakdown when (p, q) <= 0.
+struct EpiDirection {
+  using acc = double;
+  static constexpr int NV = 1;
+  static constexpr bool reduce = true;
+  double* p_new;
+  double* q;
+  DevState* st;
+  const DevState* guard;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ void operator()(int64_t i, double p, double ap, double (&part)[NV]) const {
+    p_new[i] = p;
+    q[i] = ap;
+    part[0] += p * ap;
+  }
+  __device__ void fin(double (&t)[NV]) const {
+    st->pq = t[0];
+    if (!(t[0] > 0.0) || !isfinite(t[0])) {
+      st->done = kBreakdown;
+      return;
+    }
+    st->alpha = st->gamma / t[0];
+  }
+};
+
+// y = M x.
+template <class T>
+struct EpiStore {
+  using acc = typename Store<T>::acc;
+  static constexpr int NV = 1;
+  static constexpr bool reduce = false;
+  T* y;
+  DevState* st;
+  const DevState* guard;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ void operator()(int64_t i, acc, acc m, double (&)[NV]) const { Store<T>::st(y, i, m); }
+  __device__ void fin(double (&)[NV]) const {}
+};
+
+// w = D^-1/2 A_hat D^-1/2 v (input functor InScaled supplies D^-1/2 v).
+struct EpiScaledStore {
+  using acc = double;
+  static constexpr int NV = 1;
+  static constexpr bool reduce = false;
+  double* w;
+  const double* isd;
+  DevState* st;
+  const DevState* guard;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ void operator()(int64_t i, double, double m, double (&)[NV]) const { w[i] = m * isd[i]; }
+  __device__ void fin(double (&)[NV]) const {}
+};
+
+// r = b - A x with ||r||^2 (D^-1 weighted), ||r||^2 and ||b||^2 (unweighted).
+// mode 0: initial residual (sets rr, bb, bb_hat and the first relres);
+// mode 1: exit check (true_rr, true_rr_hat); mode 2: periodic replacement
+// of the recursive residual (rr, relres).
+struct EpiResidual {
+  using acc = double;
+  static constexpr int NV = 4;
+  static constexpr bool reduce = true;
+  const double* b;
+  double* r;  // may be null: norms only
+  InvDiag invd;
+  DevState* st;
+  const DevState* guard;
+  int mode;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ void operator()(int64_t i, double, double ax, double (&part)[NV]) const {
+    const double bi = b[i];
+    const double ri = bi - ax;
+    if (r) r[i] = ri;
+    const double w = invd(i);
+    part[0] += ri * ri * w;
+    part[1] += ri * ri;
+    part[2] += bi * bi * w;
+    part[3] += bi * bi;
+  }
+  __device__ void fin(double (&t)[NV]) const {
+    if (mode == 0) {
+      st->rr = t[0];
+      st->bb = t[2];
+      st->bb_hat = t[3];
+      st->relres = t[2] > 0.0 ? sqrt(t[0]) / sqrt(t[2]) : 0.0;
+      if (!isfinite(t[0]) || !isfinite(t[2]))
+        st->done = kBreakdown;
+      else if (st->relres < st->tol)
+        st->done = kConverged;  // r_0 already meets the tolerance (or b = 0)
+    } else if (mode == 1) {
+      st->true_rr = t[0];
+      st->true_rr_hat = t[1];
+      st->bb_hat = t[3];
+    } else {
+      st->rr = t[0];
+      st->relres = st->bb > 0.0 ? sqrt(t[0]) / sqrt(st->bb) : 0.0;
+      st->refreshes += 1;
+    }
+  }
+};
+
+}  // namespace pcheb

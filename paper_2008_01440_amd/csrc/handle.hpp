@@ -1,0 +1,93 @@
+// Host-side state of a preconditioner handle and the helpers every source
+// file of the library uses (error reporting, device allocation, launches).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "pcheb.h"
+
+namespace pcheb {
+
+// Error carrying a status; thrown inside the library, caught at the ABI.
+struct Error {
+  pcheb_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(pcheb_status st, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+void set_last_error(const std::string& msg);
+
+#define PCHEB_HIP_CHECK(expr) ::pcheb::check_hip((expr), #expr)
+
+struct DeviceBuffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Handle {
+  pcheb_operator op{};
+  pcheb_params prm{};
+  int64_t n = 0;
+  int device = 0;
+  size_t elem = 8;  // bytes per element of the preconditioner vectors
+
+  // Chebyshev scalars (Sec. 3 with the Sec. 4 scaling)
+  double theta = 0, delta = 0, sigma = 0;
+  std::vector<double> rho;
+
+  // operator data owned by the handle
+  double* invd = nullptr;     // D^-1 (null for the 7-point stencil: constant 1/6)
+  void* csr_bval = nullptr;   // CSR: values of D^-1 A_hat in the storage precision
+  int lanes = 8;              // CSR: lanes per row
+  int64_t nchunks = 0;        // SELL
+  int64_t nnz_pad = 0;        // SELL
+  int64_t* sell_ptr = nullptr;
+  int32_t* sell_len = nullptr;
+  int32_t* sell_col = nullptr;
+  double* sell_aval = nullptr;  // A_hat values (float64)
+  void* sell_bval = nullptr;    // D^-1 A_hat values (storage precision)
+  int32_t* sell_perm = nullptr; // null when sigma == 1
+  void* kappa_lo = nullptr;     // STENCIL27H: float32 copy of the coefficients
+
+  // workspace for one right-hand side
+  void* s = nullptr;          // D^-1 r (storage precision)
+  void* Y[3] = {nullptr, nullptr, nullptr};  // recurrence iterates (storage precision)
+  double* r = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  double* q = nullptr;
+  double* z = nullptr;
+  DevState* st = nullptr;     // device scalars of the current solve
+  DevState* st_host = nullptr;  // pinned host mirror (two slots)
+  double* partials = nullptr;
+  unsigned int* counter = nullptr;
+
+  // graph cache for the PCG iteration pair (captured on a private stream,
+  // launched on the caller's; the legacy null stream cannot be captured)
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const double* graph_x = nullptr;
+  uint32_t graph_flags = 0;
+
+  std::vector<hipEvent_t> events;
+  std::vector<DeviceBuffer> owned;
+
+  ReduceBuf rb() const { return ReduceBuf{partials, counter}; }
+};
+
+void* dev_alloc(Handle& h, size_t bytes);
+void setup_operator(Handle& h, hipStream_t s);
+void release(Handle& h);
+
+inline uint32_t round_grid(uint64_t tiles) {
+  uint64_t g = tiles < uint64_t(kMaxGrid) ? tiles : uint64_t(kMaxGrid);
+  g = (g + kNumXcd - 1) / kNumXcd * kNumXcd;
+  return uint32_t(g < kNumXcd ? kNumXcd : g);
+}
+
+}  // namespace pcheb

@@ -1,0 +1,276 @@
+// Operator kernels: one memory-access pattern per operator kind, shared by
+// every use of the operator (Chebyshev steps, q = A p, residuals, Lanczos).
+//
+// Each kernel evaluates m_i = (M y)_i row by row and hands
+// (i, y_i, m_i) to an epilogue functor, which does the per-row arithmetic and
+// may accumulate up to kMaxReduce partial sums for a grid reduction.  The
+// input vector is read through an input functor, so a kernel can form its
+// input on the fly (p = z + beta p_old) instead of reading a stored vector.
+//
+// Interfaces
+//   In:  using acc; __device__ void prepare(); __device__ acc ld(int64_t i) const;
+//   Epi: using acc; static constexpr int NV; static constexpr bool reduce;
+//        DevState* st (may be null; written by fin); const DevState* guard (may be
+//        null; the kernel does nothing once guard->done is set); __device__ void prepare();
+//        __device__ void operator()(int64_t i, acc yi, acc mi, double (&part)[NV]) const;
+//        __device__ void fin(double (&total)[NV]) const;   // thread 0 of the last block
+//
+// M is A_hat (SCALED = false) or D^-1 A_hat (SCALED = true); for CSR and
+// SELL it is whatever value array the caller passes.
+#pragma once
+
+#include "common.hpp"
+
+namespace pcheb {
+
+template <class Epi>
+__device__ __forceinline__ bool solve_finished(const Epi& epi) {
+  return epi.guard != nullptr && epi.guard->done != kRunning;
+}
+
+template <class Epi>
+__device__ __forceinline__ void finish_reduction(const Epi& epi, double (&part)[Epi::NV], ReduceBuf rb) {
+  if constexpr (Epi::reduce) {
+    grid_reduce<Epi::NV>(part, rb, [&](double (&t)[Epi::NV]) { epi.fin(t); });
+  }
+}
+
+// ------------------------------------------------------------------ 7-point stencil
+//
+// Block = 64 (x) x 4 (y) threads; a tile is 64 x 4 columns by ZC planes.  Each
+// thread marches up its column in z keeping the planes below, at and above
+// the current point in registers, so every value is fetched from memory once
+// per tile plus the x/y neighbours that the L1/L2 already hold.
+template <bool SCALED, int ZC, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int ny, int nz,
+                                                     uint32_t tiles_x, uint32_t tiles_y, uint32_t ntiles,
+                                                     ReduceBuf rb) {
+  using acc = typename Epi::acc;
+  if (solve_finished(epi)) return;
+  in.prepare();
+  epi.prepare();
+  double part[Epi::NV];
+#pragma unroll
+  for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
+  const int64_t plane = int64_t(nx) * ny;
+  XcdTiles tiles(ntiles);
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const uint32_t tx = t % tiles_x;
+    const uint32_t rest = t / tiles_x;
+    const uint32_t ty = rest % tiles_y;
+    const uint32_t tz = rest / tiles_y;
+    const int x = int(tx) * 64 + int(threadIdx.x);
+    const int y = int(ty) * 4 + int(threadIdx.y);
+    const int z0 = int(tz) * ZC;
+    if (x >= nx || y >= ny) continue;
+    const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
+    int64_t i = x + int64_t(nx) * y + plane * z0;
+    acc below = z0 > 0 ? in.ld(i - plane) : acc(0);
+    acc centre = in.ld(i);
+    for (int z = z0; z < z1; ++z, i += plane) {
+      const acc above = z + 1 < nz ? in.ld(i + plane) : acc(0);
+      const acc w = x > 0 ? in.ld(i - 1) : acc(0);
+      const acc e = x + 1 < nx ? in.ld(i + 1) : acc(0);
+      const acc s = y > 0 ? in.ld(i - nx) : acc(0);
+      const acc n = y + 1 < ny ? in.ld(i + nx) : acc(0);
+      const acc nb = ((w + e) + (s + n)) + (below + above);
+      const acc m = SCALED ? centre - nb * acc(1.0 / 6.0) : acc(6) * centre - nb;
+      epi(i, centre, m, part);
+      below = centre;
+      centre = above;
+    }
+  }
+  finish_reduction(epi, part, rb);
+}
+
+// ------------------------------------------------------------------ 27-point harmonic stencil
+//
+// Same tiling as the 7-point kernel.  Each thread keeps the 3x3 neighbourhood
+// of y and of the cell coefficients for the planes z-1, z, z+1 in registers
+// and loads one new 3x3 plane per step.  A coefficient of 0 marks a cell
+// outside the grid (a zero-Dirichlet ghost that adds k_i to the diagonal).
+template <bool SCALED, int ZC, class KT, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT* __restrict__ kappa, int nx,
+                                                       int ny, int nz, uint32_t tiles_x, uint32_t tiles_y,
+                                                       uint32_t ntiles, ReduceBuf rb) {
+  using acc = typename Epi::acc;
+  if (solve_finished(epi)) return;
+  in.prepare();
+  epi.prepare();
+  double part[Epi::NV];
+#pragma unroll
+  for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
+  const int64_t plane = int64_t(nx) * ny;
+  XcdTiles tiles(ntiles);
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const uint32_t tx = t % tiles_x;
+    const uint32_t rest = t / tiles_x;
+    const uint32_t ty = rest % tiles_y;
+    const uint32_t tz = rest / tiles_y;
+    const int x = int(tx) * 64 + int(threadIdx.x);
+    const int y = int(ty) * 4 + int(threadIdx.y);
+    const int z0 = int(tz) * ZC;
+    if (x >= nx || y >= ny) continue;
+    const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
+    acc yv[3][3][3];
+    acc kv[3][3][3];
+    auto load_plane = [&](int slot, int zz) {
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int xx = x + dx, yy = y + dy;
+          const bool ok = zz >= 0 && zz < nz && xx >= 0 && xx < nx && yy >= 0 && yy < ny;
+          const int64_t j = xx + int64_t(nx) * yy + plane * zz;
+          yv[slot][dy + 1][dx + 1] = ok ? in.ld(j) : acc(0);
+          kv[slot][dy + 1][dx + 1] = ok ? acc(kappa[j]) : acc(0);
+        }
+      }
+    };
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    for (int z = z0; z < z1; ++z) {
+      load_plane(2, z + 1);
+      const acc ki = kv[1][1][1];
+      acc diag = acc(0), off = acc(0);
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            if (dz == 1 && dy == 1 && dx == 1) continue;
+            const acc kn = kv[dz][dy][dx];
+            if (kn > acc(0)) {
+              const acc h = acc(2) * ki * kn / (ki + kn);
+              diag += h;
+              off += h * yv[dz][dy][dx];
+            } else {
+              diag += ki;
+            }
+          }
+        }
+      }
+      const acc yc = yv[1][1][1];
+      const acc m = SCALED ? yc - off / diag : diag * yc - off;
+      const int64_t i = x + int64_t(nx) * y + plane * z;
+      epi(i, yc, m, part);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          yv[0][dy][dx] = yv[1][dy][dx];
+          kv[0][dy][dx] = kv[1][dy][dx];
+          yv[1][dy][dx] = yv[2][dy][dx];
+          kv[1][dy][dx] = kv[2][dy][dx];
+        }
+      }
+    }
+  }
+  finish_reduction(epi, part, rb);
+}
+
+// ------------------------------------------------------------------ CSR
+//
+// LANES consecutive lanes share one row (LANES = 8 for ~7 nonzeros per row,
+// 32 for ~80), read its nonzeros with unit stride and combine them with a
+// butterfly inside the group.  A tile is kBlock / LANES consecutive rows.
+template <int LANES, class Tv, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                const Tv* __restrict__ val, In in, Epi epi, int64_t n,
+                                                uint32_t ntiles, ReduceBuf rb) {
+  using acc = typename Epi::acc;
+  if (solve_finished(epi)) return;
+  in.prepare();
+  epi.prepare();
+  double part[Epi::NV];
+#pragma unroll
+  for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
+  constexpr int kRows = kBlock / LANES;
+  const int g = threadIdx.x % LANES;
+  XcdTiles tiles(ntiles);
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const int64_t row = int64_t(t) * kRows + threadIdx.x / LANES;
+    acc sum = acc(0);
+    if (row < n) {
+      const int32_t b = rowptr[row], e = rowptr[row + 1];
+      for (int32_t j = b + g; j < e; j += LANES) sum += acc(Store<Tv>::ld(val, j)) * in.ld(col[j]);
+    }
+#pragma unroll
+    for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+    if (row < n && g == 0) epi(row, in.ld(row), sum, part);
+  }
+  finish_reduction(epi, part, rb);
+}
+
+// ------------------------------------------------------------------ SELL-C-sigma, C = 64
+//
+// One wavefront per chunk of 64 (sorted) rows; chunk c stores its slot j of
+// every row contiguously (column-major), so every load of the wavefront is
+// one 64-wide unit-stride access.  Padding slots hold column 0 and value 0.
+// perm (may be null = identity) maps a sorted position to its original row.
+template <class Tv, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chunk_ptr,
+                                                 const int32_t* __restrict__ chunk_len,
+                                                 const int32_t* __restrict__ col, const Tv* __restrict__ val,
+                                                 const int32_t* __restrict__ perm, In in, Epi epi, int64_t n,
+                                                 uint32_t ntiles, ReduceBuf rb) {
+  using acc = typename Epi::acc;
+  if (solve_finished(epi)) return;
+  in.prepare();
+  epi.prepare();
+  double part[Epi::NV];
+#pragma unroll
+  for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
+  const int lane = threadIdx.x % kWave;
+  XcdTiles tiles(ntiles);  // tile = kBlock / 64 = 4 chunks
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const int64_t chunk = int64_t(t) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t pos = chunk * kWave + lane;
+    if (chunk * kWave >= n) continue;
+    const int64_t base = chunk_ptr[chunk];
+    const int32_t len = chunk_len[chunk];
+    acc sum = acc(0);
+    for (int32_t j = 0; j < len; ++j) {
+      const int64_t e = base + int64_t(j) * kWave + lane;
+      sum += acc(Store<Tv>::ld(val, e)) * in.ld(col[e]);
+    }
+    if (pos < n) {
+      const int64_t row = perm ? int64_t(perm[pos]) : pos;
+      epi(row, in.ld(row), sum, part);
+    }
+  }
+  finish_reduction(epi, part, rb);
+}
+
+// ------------------------------------------------------------------ input functors
+
+template <class T>
+struct InVec {
+  using acc = typename Store<T>::acc;
+  const T* p;
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ acc ld(int64_t i) const { return Store<T>::ld(p, i); }
+};
+
+// p = z + beta * p_old, formed where it is read (beta from the solver state).
+struct InDirection {
+  using acc = double;
+  const double* z;
+  const double* p_old;
+  const DevState* st;
+  double beta;
+  __device__ __forceinline__ void prepare() { beta = st->beta; }
+  __device__ __forceinline__ double ld(int64_t i) const { return z[i] + beta * p_old[i]; }
+};
+
+// v scaled by D^-1/2 (for the symmetric scaled operator of the Lanczos estimator).
+struct InScaled {
+  using acc = double;
+  const double* v;
+  const double* isd;  // 1 / sqrt(diag)
+  __device__ __forceinline__ void prepare() {}
+  __device__ __forceinline__ double ld(int64_t i) const { return v[i] * isd[i]; }
+};
+
+}  // namespace pcheb

@@ -1,0 +1,860 @@
+// pcheb: set-up, preconditioner application, operator product and the PCG
+// driver of the Newton-Chebyshev preconditioned CG (arXiv:2008.01440) on
+// gfx950.  The C ABI is declared in include/pcheb.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dispatch.hpp"
+#include "handle.hpp"
+
+namespace pcheb {
+
+// ================================================================ errors and memory
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(pcheb_status st, const std::string& msg) { throw Error{st, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const pcheb_status st = (e == hipErrorOutOfMemory) ? PCHEB_OOM : PCHEB_HIP;
+  fail(st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* dev_alloc(Handle& h, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? PCHEB_OOM : PCHEB_HIP,
+         "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  }
+  h.owned.push_back(DeviceBuffer{p, bytes});
+  return p;
+}
+
+void release(Handle& h) {
+  if (h.graph_exec) (void)hipGraphExecDestroy(h.graph_exec);
+  h.graph_exec = nullptr;
+  if (h.capture_stream) (void)hipStreamDestroy(h.capture_stream);
+  h.capture_stream = nullptr;
+  for (hipEvent_t e : h.events) (void)hipEventDestroy(e);
+  h.events.clear();
+  if (h.st_host) (void)hipHostFree(h.st_host);
+  h.st_host = nullptr;
+  for (auto& b : h.owned) (void)hipFree(b.ptr);
+  h.owned.clear();
+}
+
+static size_t storage_bytes(int prec) { return prec == PCHEB_F64 ? 8 : (prec == PCHEB_F32 ? 4 : 2); }
+
+// ================================================================ elementwise kernels
+
+static uint32_t flat_grid(int64_t n) {
+  const int64_t per_block = int64_t(kBlock) * 4;
+  int64_t g = (n + per_block - 1) / per_block;
+  g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxGrid));
+  return uint32_t(g);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  GRID_STRIDE(i, n) p[i] = v;
+}
+
+__global__ void k_to_float(const double* a, float* b, int64_t n) {
+  GRID_STRIDE(i, n) b[i] = float(a[i]);
+}
+
+// CSR diagonal (sum of entries on the diagonal) -> 1/d; flags d <= 0.
+__global__ void k_csr_invdiag(const int32_t* rowptr, const int32_t* col, const double* val, int64_t n,
+                              double* invd, int* bad) {
+  GRID_STRIDE(i, n) {
+    double d = 0.0;
+    for (int32_t j = rowptr[i]; j < rowptr[i + 1]; ++j)
+      if (col[j] == i) d += val[j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      atomicOr(bad, 1);
+      invd[i] = 0.0;
+    } else {
+      invd[i] = 1.0 / d;
+    }
+  }
+}
+
+// 27-point harmonic operator diagonal: sum of the 26 harmonic means, k_i for
+// every neighbour outside the grid.  Flags coefficients <= 0.
+__global__ void k_h27_invdiag(const double* kappa, int nx, int ny, int nz, double* invd, int* bad) {
+  const int64_t n = int64_t(nx) * ny * nz;
+  GRID_STRIDE(i, n) {
+    const int x = int(i % nx);
+    const int y = int((i / nx) % ny);
+    const int z = int(i / (int64_t(nx) * ny));
+    const double ki = kappa[i];
+    if (!(ki > 0.0) || !isfinite(ki)) {
+      atomicOr(bad, 1);
+      invd[i] = 0.0;
+      continue;
+    }
+    double d = 0.0;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (!dz && !dy && !dx) continue;
+          const int xx = x + dx, yy = y + dy, zz = z + dz;
+          if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) {
+            d += ki;
+          } else {
+            const double kn = kappa[xx + int64_t(nx) * (yy + int64_t(ny) * zz)];
+            d += kn > 0.0 ? 2.0 * ki * kn / (ki + kn) : ki;
+          }
+        }
+    invd[i] = 1.0 / d;
+  }
+}
+
+// Values of D^-1 A_hat in the storage precision (row i scaled by 1/d_i).
+template <class T>
+__global__ void k_scale_rows(const int32_t* rowptr, const double* val, const double* invd, int64_t n, T* out) {
+  GRID_STRIDE(i, n) {
+    const double w = invd[i];
+    for (int32_t j = rowptr[i]; j < rowptr[i + 1]; ++j) Store<T>::st(out, j, typename Store<T>::acc(val[j] * w));
+  }
+}
+
+// Fill the SELL-C-sigma arrays (C = 64) from CSR; padding gets column 0, value 0.
+template <class T>
+__global__ void k_sell_fill(const int32_t* rowptr, const int32_t* col, const double* val, const double* invd,
+                            const int32_t* perm, const int64_t* cptr, const int32_t* clen, int64_t n,
+                            int64_t nchunks, int32_t* scol, double* saval, T* sbval) {
+  GRID_STRIDE(pos, nchunks * kWave) {
+    const int64_t c = pos / kWave;
+    const int lane = int(pos % kWave);
+    const int32_t len = clen[c];
+    int64_t row = -1;
+    int32_t b = 0, rl = 0;
+    if (pos < n) {
+      row = perm ? perm[pos] : pos;
+      b = rowptr[row];
+      rl = rowptr[row + 1] - b;
+    }
+    for (int32_t j = 0; j < len; ++j) {
+      const int64_t e = cptr[c] + int64_t(j) * kWave + lane;
+      if (j < rl) {
+        scol[e] = col[b + j];
+        saval[e] = val[b + j];
+        Store<T>::st(sbval, e, typename Store<T>::acc(val[b + j] * invd[row]));
+      } else {
+        scol[e] = 0;
+        saval[e] = 0.0;
+        Store<T>::st(sbval, e, typename Store<T>::acc(0));
+      }
+    }
+  }
+}
+
+// x0 = 0: x = 0, r = b, p_old = 0 and the norms of b.
+__global__ void k_start_zero(const double* b, double* x, double* r, double* p_old, InvDiag invd, int64_t n,
+                             DevState* st, ReduceBuf rb) {
+  double part[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double bi = b[i];
+    x[i] = 0.0;
+    r[i] = bi;
+    p_old[i] = 0.0;
+    part[0] += bi * bi * invd(i);
+    part[1] += bi * bi;
+  }
+  grid_reduce<2>(part, rb, [&](double (&t)[2]) {
+    st->bb = t[0];
+    st->rr = t[0];
+    st->bb_hat = t[1];
+    st->relres = t[0] > 0.0 ? 1.0 : 0.0;
+    if (!(t[0] > 0.0)) st->done = isfinite(t[0]) ? kConverged : kBreakdown;
+  });
+}
+
+// Preconditioner input: s = D^-1 r and y_0 = s / theta' in the storage precision.
+template <class T>
+__global__ void k_prep(const double* r, T* s, T* y0, InvDiag invd, double inv_theta, int64_t n,
+                       const DevState* guard) {
+  if (guard && guard->done != kRunning) return;
+  GRID_STRIDE(i, n) {
+    const double si = r[i] * invd(i);
+    Store<T>::st(s, i, typename Store<T>::acc(si));
+    Store<T>::st(y0, i, typename Store<T>::acc(si * inv_theta));
+  }
+}
+
+// Degree 0: z = D^-1 r / theta' (the diagonal preconditioner), optionally with
+// the dot products and beta of the last recurrence step.
+__global__ void k_jacobi(const double* r, double* z, const double* q, InvDiag invd, double inv_theta, int64_t n,
+                         DevState* st, const DevState* guard, ReduceBuf rb, int dots, int init, int flexible) {
+  if (guard && guard->done != kRunning) return;
+  double part[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double ri = r[i];
+    const double zi = ri * invd(i) * inv_theta;
+    z[i] = zi;
+    part[0] += ri * zi;
+    if (flexible) part[1] += zi * q[i];
+  }
+  if (dots) {
+    grid_reduce<2>(part, rb, [&](double (&t)[2]) {
+      EpiChebLast<double, true, true>::finish_beta(st, t[0], t[1], init, flexible);
+    });
+  }
+}
+
+// Iteration update x += alpha p, r -= alpha q with ||r||^2 (D^-1 weighted), the
+// stop test on the device, and the next preconditioner input fused in:
+//   MODE 0 (k >= 1): s = D^-1 r, y_0 = s / theta';
+//   MODE 1 (k = 0):  z = D^-1 r / theta' with (r, z), (z, q) and beta;
+//   MODE 2:          nothing else (the residual is refreshed before the next step).
+template <class T, int MODE>
+__global__ void k_update(double* x, double* r, const double* p, const double* q, InvDiag invd, T* s, T* y0,
+                         double* z, double inv_theta, int64_t n, DevState* st, ReduceBuf rb) {
+  if (st->done != kRunning) return;
+  const double alpha = st->alpha;
+  const int flexible = st->flexible;
+  double part[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double qi = q[i];
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * qi;
+    r[i] = ri;
+    const double w = invd(i);
+    part[0] += ri * ri * w;
+    if (MODE == 0) {
+      const double si = ri * w;
+      Store<T>::st(s, i, typename Store<T>::acc(si));
+      Store<T>::st(y0, i, typename Store<T>::acc(si * inv_theta));
+    } else if (MODE == 1) {
+      const double zi = ri * w * inv_theta;
+      z[i] = zi;
+      part[1] += ri * zi;
+      if (flexible) part[2] += zi * qi;
+    }
+  }
+  grid_reduce<3>(part, rb, [&](double (&t)[3]) {
+    st->rr = t[0];
+    st->iter += 1;
+    st->relres = sqrt(t[0]) / sqrt(st->bb);
+    if (!isfinite(t[0])) {
+      st->done = kBreakdown;
+    } else if (st->relres < st->tol) {
+      st->done = kConverged;
+    } else if (st->iter >= st->maxit) {
+      st->done = kMaxIter;
+    } else if (MODE == 1) {
+      EpiChebLast<double, true, true>::finish_beta(st, t[1], t[2], 0, flexible);
+    }
+  });
+}
+
+// ================================================================ preconditioner
+
+template <class T>
+struct Coef {
+  using acc = typename Store<T>::acc;
+  acc a, b, c;
+};
+
+template <class T>
+static Coef<T> step_coef(const Handle& h, int j) {
+  using acc = typename Store<T>::acc;
+  Coef<T> c;
+  c.a = acc(2.0 * h.sigma * h.rho[j]);
+  c.b = acc(j >= 1 ? h.rho[j] * h.rho[j - 1] : 0.0);
+  c.c = acc(2.0 * h.rho[j] / h.delta);
+  return c;
+}
+
+static InvDiag invdiag(const Handle& h) { return InvDiag{h.invd, h.invd ? 0.0 : 1.0 / 6.0}; }
+
+// Optional timing of the middle steps (2 .. k-1) of each application.
+struct StepTimer {
+  std::vector<hipEvent_t>* pool = nullptr;
+  size_t used = 0;
+  hipEvent_t next(Handle& h) {
+    if (used == h.events.size()) {
+      hipEvent_t e;
+      PCHEB_HIP_CHECK(hipEventCreate(&e));
+      h.events.push_back(e);
+    }
+    return h.events[used++];
+  }
+};
+
+// Steps 1..k of Alg. 2 on the prepared input (s, y_0 = Y[0]); the last step
+// writes z in float64.  dots: reduce (r, z), (z, q) and form beta (inside a solve).
+template <class T>
+static void enqueue_steps(Handle& h, double* z, const double* r, const double* q, bool dots, int init, int flexible,
+                          DevState* guard, StepTimer* timer, hipStream_t s) {
+  const int k = h.prm.k;
+  T* Y[3] = {reinterpret_cast<T*>(h.Y[0]), reinterpret_cast<T*>(h.Y[1]), reinterpret_cast<T*>(h.Y[2])};
+  const T* sv = reinterpret_cast<const T*>(h.s);
+  for (int j = 1; j <= k; ++j) {
+    if (timer && k >= 3 && j == 2) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
+    const Coef<T> c = step_coef<T>(h, j);
+    const T* yin = Y[(j - 1) % 3];
+    const T* yprev = j >= 2 ? Y[(j - 2) % 3] : nullptr;
+    if (j < k) {
+      T* yout = Y[j % 3];
+      if (j == 1)
+        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, true>{yprev, sv, yout, c.a, c.b, c.c, nullptr, guard}, s);
+      else
+        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, false>{yprev, sv, yout, c.a, c.b, c.c, nullptr, guard}, s);
+    } else {
+      if (j == 1) {
+        if (dots)
+          launch_bop<T>(h, InVec<T>{yin},
+                        EpiChebLast<T, true, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, flexible}, s);
+        else
+          launch_bop<T>(h, InVec<T>{yin},
+                        EpiChebLast<T, true, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0}, s);
+      } else {
+        if (dots)
+          launch_bop<T>(h, InVec<T>{yin},
+                        EpiChebLast<T, false, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, flexible}, s);
+        else
+          launch_bop<T>(h, InVec<T>{yin},
+                        EpiChebLast<T, false, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0}, s);
+      }
+    }
+    if (timer && k >= 3 && j == k - 1) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
+  }
+}
+
+template <class T>
+static void enqueue_apply(Handle& h, const double* r, double* z, hipStream_t s) {
+  const int64_t n = h.n;
+  if (h.prm.k == 0) {
+    k_jacobi<<<flat_grid(n), kBlock, 0, s>>>(r, z, nullptr, invdiag(h), 1.0 / h.theta, n, h.st, nullptr, h.rb(), 0, 0,
+                                             0);
+    return;
+  }
+  k_prep<T><<<flat_grid(n), kBlock, 0, s>>>(r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
+                                           1.0 / h.theta, n, nullptr);
+  enqueue_steps<T>(h, z, r, nullptr, false, 0, 0, nullptr, nullptr, s);
+}
+
+#define PCHEB_BY_PREC(h, FN, ...)                      \
+  do {                                                 \
+    switch ((h).prm.prec) {                            \
+      case PCHEB_F64:                                  \
+        FN<double>(__VA_ARGS__);                       \
+        break;                                         \
+      case PCHEB_F32:                                  \
+        FN<float>(__VA_ARGS__);                        \
+        break;                                         \
+      default:                                         \
+        FN<bf16>(__VA_ARGS__);                         \
+        break;                                         \
+    }                                                  \
+  } while (0)
+
+// ================================================================ set-up
+
+static void validate(const pcheb_operator* A, const pcheb_params* p) {
+  if (!A || !p) fail(PCHEB_INVALID, "null operator or parameters");
+  if (p->k < 0 || p->k > 1000) fail(PCHEB_INVALID, "degree k must be in [0, 1000]");
+  if (!(p->lambda_min > 0.0) || !(p->lambda_max > p->lambda_min) || !std::isfinite(p->lambda_max))
+    fail(PCHEB_INVALID, "need 0 < lambda_min < lambda_max");
+  if (!(p->theta_scale >= 1.0) || !std::isfinite(p->theta_scale)) fail(PCHEB_INVALID, "theta_scale must be >= 1");
+  if (p->prec < PCHEB_F64 || p->prec > PCHEB_BF16) fail(PCHEB_INVALID, "unknown precision");
+  if (A->n <= 0) fail(PCHEB_INVALID, "n must be positive");
+  switch (A->kind) {
+    case PCHEB_OP_CSR:
+    case PCHEB_OP_SELL:
+      if (!A->rowptr || !A->colind || !A->values) fail(PCHEB_INVALID, "CSR arrays must be non-null");
+      if (A->nnz < 0 || A->nnz >= (int64_t(1) << 31)) fail(PCHEB_INVALID, "nnz must be below 2^31");
+      if (A->n >= (int64_t(1) << 31)) fail(PCHEB_INVALID, "CSR row count must be below 2^31");
+      if (A->kind == PCHEB_OP_SELL) {
+        if (A->sell_C != 0 && A->sell_C != kWave) fail(PCHEB_INVALID, "SELL chunk height must be 64");
+        if (A->sell_sigma < 1) fail(PCHEB_INVALID, "SELL sigma must be >= 1");
+      }
+      break;
+    case PCHEB_OP_STENCIL7:
+    case PCHEB_OP_STENCIL27H:
+      if (A->nx <= 0 || A->ny <= 0 || A->nz <= 0) fail(PCHEB_INVALID, "grid dimensions must be positive");
+      if (int64_t(A->nx) * A->ny * A->nz != A->n) fail(PCHEB_INVALID, "n must equal nx*ny*nz");
+      if (A->n >= (int64_t(1) << 32)) fail(PCHEB_INVALID, "grid too large");
+      if (A->kind == PCHEB_OP_STENCIL27H && !A->cell_coeff) fail(PCHEB_INVALID, "cell_coeff must be non-null");
+      break;
+    default:
+      fail(PCHEB_INVALID, "unknown operator kind");
+  }
+}
+
+static int pick_lanes(int64_t n, int64_t nnz) {
+  const double avg = n > 0 ? double(nnz) / double(n) : 1.0;
+  if (avg <= 5.0) return 4;
+  if (avg <= 10.0) return 8;
+  if (avg <= 20.0) return 16;
+  if (avg <= 100.0) return 32;
+  return 64;
+}
+
+// Scalars of eq. rhocheb with the Sec. 4 scaling theta' = s theta.
+static void chebyshev_scalars(Handle& h) {
+  const pcheb_params& p = h.prm;
+  h.theta = p.theta_scale * 0.5 * (p.lambda_max + p.lambda_min);
+  h.delta = 0.5 * (p.lambda_max - p.lambda_min);
+  h.sigma = h.theta / h.delta;
+  h.rho.assign(size_t(p.k) + 1, 0.0);
+  h.rho[0] = 1.0 / h.sigma;
+  for (int j = 1; j <= p.k; ++j) h.rho[j] = 1.0 / (2.0 * h.sigma - h.rho[j - 1]);
+}
+
+template <class T>
+static void build_scaled_values(Handle& h, hipStream_t s) {
+  const pcheb_operator& op = h.op;
+  if (op.kind == PCHEB_OP_CSR) {
+    h.csr_bval = dev_alloc(h, size_t(op.nnz) * sizeof(T));
+    k_scale_rows<T><<<flat_grid(h.n), kBlock, 0, s>>>(op.rowptr, op.values, h.invd, h.n,
+                                                     reinterpret_cast<T*>(h.csr_bval));
+    PCHEB_HIP_CHECK(hipGetLastError());
+  } else if (op.kind == PCHEB_OP_SELL) {
+    // row lengths on the host, sorted within windows of sigma rows (longest first)
+    std::vector<int32_t> rp(size_t(h.n) + 1);
+    PCHEB_HIP_CHECK(hipMemcpyAsync(rp.data(), op.rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PCHEB_HIP_CHECK(hipStreamSynchronize(s));
+    if (rp[0] != 0 || int64_t(rp[size_t(h.n)]) != op.nnz) fail(PCHEB_INVALID, "rowptr does not span nnz");
+    const int sigma = std::max(1, op.sell_sigma);
+    std::vector<int32_t> perm(size_t(h.n));
+    std::iota(perm.begin(), perm.end(), 0);
+    if (sigma > 1) {
+      for (int64_t w = 0; w < h.n; w += sigma) {
+        const int64_t e = std::min<int64_t>(h.n, w + sigma);
+        std::stable_sort(perm.begin() + w, perm.begin() + e, [&](int32_t a, int32_t b) {
+          return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+        });
+      }
+    }
+    h.nchunks = (h.n + kWave - 1) / kWave;
+    std::vector<int64_t> cptr(size_t(h.nchunks));
+    std::vector<int32_t> clen(size_t(h.nchunks));
+    int64_t off = 0;
+    for (int64_t c = 0; c < h.nchunks; ++c) {
+      int32_t m = 0;
+      for (int64_t l = 0; l < kWave && c * kWave + l < h.n; ++l) {
+        const int32_t row = perm[size_t(c * kWave + l)];
+        m = std::max(m, rp[row + 1] - rp[row]);
+      }
+      cptr[size_t(c)] = off;
+      clen[size_t(c)] = m;
+      off += int64_t(m) * kWave;
+    }
+    h.nnz_pad = off;
+    h.sell_ptr = static_cast<int64_t*>(dev_alloc(h, cptr.size() * sizeof(int64_t)));
+    h.sell_len = static_cast<int32_t*>(dev_alloc(h, clen.size() * sizeof(int32_t)));
+    h.sell_col = static_cast<int32_t*>(dev_alloc(h, size_t(off) * sizeof(int32_t)));
+    h.sell_aval = static_cast<double*>(dev_alloc(h, size_t(off) * sizeof(double)));
+    h.sell_bval = dev_alloc(h, size_t(off) * sizeof(T));
+    int32_t* dperm = nullptr;
+    if (sigma > 1) {
+      h.sell_perm = static_cast<int32_t*>(dev_alloc(h, perm.size() * sizeof(int32_t)));
+      dperm = h.sell_perm;
+      PCHEB_HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    PCHEB_HIP_CHECK(hipMemcpyAsync(h.sell_ptr, cptr.data(), cptr.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    PCHEB_HIP_CHECK(hipMemcpyAsync(h.sell_len, clen.data(), clen.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    k_sell_fill<T><<<flat_grid(h.nchunks * kWave), kBlock, 0, s>>>(
+        op.rowptr, op.colind, op.values, h.invd, dperm, h.sell_ptr, h.sell_len, h.n, h.nchunks, h.sell_col,
+        h.sell_aval, reinterpret_cast<T*>(h.sell_bval));
+    PCHEB_HIP_CHECK(hipGetLastError());
+    PCHEB_HIP_CHECK(hipStreamSynchronize(s));  // host vectors above go out of scope
+  }
+}
+
+// Diagonal (D^-1), NOT_SPD check and the float32 coefficient copy.
+void setup_operator(Handle& h, hipStream_t s) {
+  const pcheb_operator& op = h.op;
+  const int64_t n = h.n;
+  PCHEB_HIP_CHECK(hipGetDevice(&h.device));
+  int* bad = static_cast<int*>(dev_alloc(h, sizeof(int)));
+  PCHEB_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
+  if (op.kind == PCHEB_OP_CSR || op.kind == PCHEB_OP_SELL) {
+    h.invd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
+    k_csr_invdiag<<<flat_grid(n), kBlock, 0, s>>>(op.rowptr, op.colind, op.values, n, h.invd, bad);
+    h.lanes = pick_lanes(n, op.nnz);
+  } else if (op.kind == PCHEB_OP_STENCIL27H) {
+    h.invd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
+    k_h27_invdiag<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, op.nx, op.ny, op.nz, h.invd, bad);
+    if (h.prm.prec != PCHEB_F64) {
+      h.kappa_lo = dev_alloc(h, size_t(n) * sizeof(float));
+      k_to_float<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, static_cast<float*>(h.kappa_lo), n);
+    }
+  }
+  PCHEB_HIP_CHECK(hipGetLastError());
+  int bad_host = 0;
+  PCHEB_HIP_CHECK(hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  PCHEB_HIP_CHECK(hipStreamSynchronize(s));
+  if (bad_host) fail(PCHEB_NOT_SPD, "operator has a non-positive diagonal entry or coefficient");
+}
+
+// Recurrence scalars, the scaled operator copies and the solve workspace.
+static void setup_preconditioner(Handle& h, hipStream_t s) {
+  const int64_t n = h.n;
+  chebyshev_scalars(h);
+  h.elem = storage_bytes(h.prm.prec);
+  PCHEB_BY_PREC(h, build_scaled_values, h, s);
+
+  h.s = dev_alloc(h, size_t(n) * h.elem);
+  for (auto& y : h.Y) y = dev_alloc(h, size_t(n) * h.elem);
+  h.r = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
+  h.p[0] = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
+  h.p[1] = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
+  h.q = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
+  h.z = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
+  h.st = static_cast<DevState*>(dev_alloc(h, sizeof(DevState)));
+  h.partials = static_cast<double*>(dev_alloc(h, size_t(kMaxGrid) * kMaxReduce * sizeof(double)));
+  h.counter = static_cast<unsigned int*>(dev_alloc(h, sizeof(unsigned int)));
+  PCHEB_HIP_CHECK(hipMemsetAsync(h.counter, 0, sizeof(unsigned int), s));
+  PCHEB_HIP_CHECK(hipMemsetAsync(h.st, 0, sizeof(DevState), s));
+  PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h.st_host), 2 * sizeof(DevState), hipHostMallocDefault));
+  std::memset(h.st_host, 0, 2 * sizeof(DevState));
+  PCHEB_HIP_CHECK(hipStreamSynchronize(s));
+}
+
+static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs) {
+  const int64_t n = A->n;
+  const size_t e = storage_bytes(p->prec);
+  size_t b = 64;
+  if (A->kind == PCHEB_OP_CSR) b += size_t(n) * 8 + size_t(A->nnz) * e;
+  if (A->kind == PCHEB_OP_SELL) {
+    const int64_t chunks = (n + kWave - 1) / kWave;
+    b += size_t(n) * 8 + size_t(chunks) * 12 + size_t(A->nnz) * (4 + 8 + e);
+    if (A->sell_sigma > 1) b += size_t(n) * 4;
+  }
+  if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 4 : 0);
+  const size_t per_rhs = size_t(n) * (4 * e + 5 * 8);
+  b += size_t(std::max(1, nrhs)) * per_rhs;
+  b += size_t(kMaxGrid) * kMaxReduce * 8 + sizeof(DevState) + 256;
+  return b;
+}
+
+// ================================================================ PCG driver
+
+template <class T>
+static void enqueue_prep_or_jacobi(Handle& h, int init, int flexible, StepTimer* timer, hipStream_t s) {
+  const int64_t n = h.n;
+  if (h.prm.k == 0) {
+    k_jacobi<<<flat_grid(n), kBlock, 0, s>>>(h.r, h.z, h.q, invdiag(h), 1.0 / h.theta, n, h.st, h.st, h.rb(), 1, init,
+                                             flexible);
+    return;
+  }
+  k_prep<T><<<flat_grid(n), kBlock, 0, s>>>(h.r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
+                                           1.0 / h.theta, n, h.st);
+  enqueue_steps<T>(h, h.z, h.r, h.q, true, init, flexible, h.st, timer, s);
+}
+
+// One PCG iteration: q = A (z + beta p_old), the update with the fused
+// preconditioner input, and the k recurrence steps (beta formed on the device).
+template <class T>
+static void enqueue_iteration(Handle& h, double* x, const double* b, int cur, int flexible, bool refresh,
+                              StepTimer* timer, hipStream_t s) {
+  const int64_t n = h.n;
+  DevState* st = h.st;
+  double* p_new = h.p[cur ^ 1];
+  launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0}, EpiDirection{p_new, h.q, st, st}, s);
+  const uint32_t g = flat_grid(n);
+  if (refresh) {
+    k_update<T, 2><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), nullptr, nullptr, nullptr, 0.0, n, st,
+                                        h.rb());
+    launch_ahat(h, InVec<double>{x}, EpiResidual{b, h.r, invdiag(h), st, st, 2}, s);
+    enqueue_prep_or_jacobi<T>(h, 0, flexible, timer, s);
+    return;
+  }
+  if (h.prm.k == 0) {
+    k_update<double, 1><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), nullptr, nullptr, h.z, 1.0 / h.theta, n,
+                                             st, h.rb());
+  } else {
+    k_update<T, 0><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), reinterpret_cast<T*>(h.s),
+                                        reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb());
+    enqueue_steps<T>(h, h.z, h.r, h.q, true, 0, flexible, st, timer, s);
+  }
+}
+
+template <class T>
+static void capture_pair(Handle& h, double* x, const double* b, int flexible) {
+  if (!h.capture_stream) PCHEB_HIP_CHECK(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking));
+  hipStream_t s = h.capture_stream;
+  hipGraph_t graph = nullptr;
+  PCHEB_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue_iteration<T>(h, x, b, 0, flexible, false, nullptr, s);
+    enqueue_iteration<T>(h, x, b, 1, flexible, false, nullptr, s);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  PCHEB_HIP_CHECK(hipStreamEndCapture(s, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  PCHEB_HIP_CHECK(e);
+  if (h.graph_exec) (void)hipGraphExecDestroy(h.graph_exec);
+  h.graph_exec = exec;
+}
+
+template <class T>
+static pcheb_status solve_impl(Handle& h, const double* b, double* x, double tol, int maxit, uint32_t flags,
+                               pcg_stats* stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = h.n;
+  const int flexible = (flags & PCG_FLEXIBLE) ? 1 : 0;
+  const bool timed = (flags & PCG_TIME_KERNELS) != 0;
+  const bool refresh = (flags & PCG_REFRESH) != 0;
+  const bool use_graph = !(flags & (PCG_NO_GRAPH | PCG_TIME_KERNELS | PCG_REFRESH));
+  StepTimer timer;
+  StepTimer* tp = timed ? &timer : nullptr;
+
+  DevState init{};
+  init.tol = tol;
+  init.maxit = maxit;
+  init.flexible = flexible;
+  DevState* hs = h.st_host;
+  hs[0] = init;
+  PCHEB_HIP_CHECK(hipMemcpyAsync(h.st, &hs[0], sizeof(DevState), hipMemcpyHostToDevice, s));
+  if (flags & PCG_X0_GIVEN) {
+    k_fill<<<flat_grid(n), kBlock, 0, s>>>(h.p[0], n, 0.0);
+    launch_ahat(h, InVec<double>{x}, EpiResidual{b, h.r, invdiag(h), h.st, nullptr, 0}, s);
+  } else {
+    k_start_zero<<<flat_grid(n), kBlock, 0, s>>>(b, x, h.r, h.p[0], invdiag(h), n, h.st, h.rb());
+  }
+  enqueue_prep_or_jacobi<T>(h, 1, flexible, tp, s);
+  PCHEB_HIP_CHECK(hipGetLastError());
+
+  if (use_graph && (h.graph_exec == nullptr || h.graph_x != x || h.graph_flags != uint32_t(flexible))) {
+    capture_pair<T>(h, x, b, flexible);
+    h.graph_x = x;
+    h.graph_flags = uint32_t(flexible);
+  }
+
+  int cur = 0;
+  int64_t issued = 0;
+  int chunk = 2;
+  int slot = 0;
+  bool have_prev = false;
+  hipEvent_t ev[2];
+  PCHEB_HIP_CHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  PCHEB_HIP_CHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  try {
+    for (;;) {
+      for (int it = 0; it < chunk; ++it) {
+        const bool ref = refresh && issued > 0 && (issued + 1) % 50 == 0;
+        if (use_graph) {
+          if (it % 2 == 0) PCHEB_HIP_CHECK(hipGraphLaunch(h.graph_exec, s));
+        } else {
+          enqueue_iteration<T>(h, x, b, cur, flexible, ref, tp, s);
+          cur ^= 1;
+        }
+        ++issued;
+      }
+      PCHEB_HIP_CHECK(hipGetLastError());
+      PCHEB_HIP_CHECK(hipMemcpyAsync(&hs[slot], h.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+      PCHEB_HIP_CHECK(hipEventRecord(ev[slot], s));
+      if (have_prev) {
+        PCHEB_HIP_CHECK(hipEventSynchronize(ev[slot ^ 1]));
+        if (hs[slot ^ 1].done != kRunning) break;
+      }
+      have_prev = true;
+      slot ^= 1;
+      if (chunk < 16) chunk *= 2;
+      if (issued > int64_t(maxit) + 64) {
+        // the device stops at maxit; wait for the last copy and leave
+        PCHEB_HIP_CHECK(hipEventSynchronize(ev[slot ^ 1]));
+        break;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    throw;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+
+  // true residual at exit
+  launch_ahat(h, InVec<double>{x}, EpiResidual{b, nullptr, invdiag(h), h.st, nullptr, 1}, s);
+  PCHEB_HIP_CHECK(hipGetLastError());
+  PCHEB_HIP_CHECK(hipMemcpyAsync(&hs[0], h.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  PCHEB_HIP_CHECK(hipStreamSynchronize(s));
+  const DevState fin = hs[0];
+
+  pcheb_status status = PCHEB_OK;
+  if (fin.done == kBreakdown)
+    status = PCHEB_BREAKDOWN;
+  else if (fin.done != kConverged)
+    status = PCHEB_NOT_CONVERGED;
+  if (stats) {
+    pcg_stats& o = *stats;
+    std::memset(&o, 0, sizeof(o));
+    o.iters = fin.iter;
+    o.converged = fin.done == kConverged;
+    o.status = status;
+    o.relres = fin.relres;
+    o.relres_true = fin.bb > 0 ? std::sqrt(fin.true_rr) / std::sqrt(fin.bb) : 0.0;
+    o.relres_true_hat = fin.bb_hat > 0 ? std::sqrt(fin.true_rr_hat) / std::sqrt(fin.bb_hat) : 0.0;
+    const int64_t k = h.prm.k;
+    const int64_t applies = fin.iter == 0 ? (fin.done == kConverged ? 0 : 1)
+                                          : (fin.done == kMaxIter ? fin.iter + 1 : fin.iter);
+    o.n_spmv = fin.iter + k * applies + ((flags & PCG_X0_GIVEN) ? 1 : 0);
+    o.n_dot = applies + 2 * int64_t(fin.iter) + (flexible ? std::max<int64_t>(0, applies - 1) : 0);
+    if (timed && h.prm.k >= 3) {
+      // applications that ran: the initial one plus one per non-final iteration
+      const size_t pairs = std::min(timer.used / 2, size_t(applies));
+      double ms = 0.0;
+      for (size_t i = 0; i < pairs; ++i) {
+        float t = 0.f;
+        PCHEB_HIP_CHECK(hipEventElapsedTime(&t, h.events[2 * i], h.events[2 * i + 1]));
+        ms += t;
+      }
+      o.step_ms = ms;
+      o.step_launches = int64_t(pairs) * (h.prm.k - 2);
+    }
+    o.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+}  // namespace pcheb
+
+// ================================================================ C ABI
+
+using namespace pcheb;
+
+template <class F>
+static pcheb_status guarded(F&& f) {
+  try {
+    set_last_error("");
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return PCHEB_OOM;
+  } catch (...) {
+    set_last_error("unexpected internal error");
+    return PCHEB_HIP;
+  }
+}
+
+extern "C" {
+
+pcheb_status pcheb_setup(const pcheb_operator* A, const pcheb_params* p, hipStream_t stream, pcheb_handle* out) {
+  return guarded([&]() -> pcheb_status {
+    if (!out) fail(PCHEB_INVALID, "out is null");
+    validate(A, p);
+    Handle* h = new Handle();
+    h->op = *A;
+    h->prm = *p;
+    h->n = A->n;
+    try {
+      setup_operator(*h, stream);
+      setup_preconditioner(*h, stream);
+    } catch (...) {
+      release(*h);
+      delete h;
+      throw;
+    }
+    *out = reinterpret_cast<pcheb_handle>(h);
+    return PCHEB_OK;
+  });
+}
+
+static Handle* as_handle(pcheb_handle h) {
+  if (!h) fail(PCHEB_INVALID, "null handle");
+  return reinterpret_cast<Handle*>(h);
+}
+
+static void check_vectors(const Handle& h, const void* a, const void* b, int32_t nrhs, int64_t ld) {
+  if (!a || !b) fail(PCHEB_INVALID, "null vector");
+  if (nrhs != 1) fail(PCHEB_INVALID, "this build supports nrhs = 1");
+  if (ld < h.n) fail(PCHEB_INVALID, "ld must be >= n");
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  const size_t bytes = size_t(h.n) * 8;
+  if (pa < pb + bytes && pb < pa + bytes) fail(PCHEB_INVALID, "input and output vectors overlap");
+}
+
+pcheb_status pcheb_apply(pcheb_handle hh, const double* r, double* z, int32_t nrhs, int64_t ld, hipStream_t stream) {
+  return guarded([&]() -> pcheb_status {
+    Handle& h = *as_handle(hh);
+    check_vectors(h, r, z, nrhs, ld);
+    PCHEB_BY_PREC(h, enqueue_apply, h, r, z, stream);
+    PCHEB_HIP_CHECK(hipGetLastError());
+    return PCHEB_OK;
+  });
+}
+
+pcheb_status pcheb_matvec(pcheb_handle hh, const double* x, double* y, int32_t nrhs, int64_t ld, hipStream_t stream) {
+  return guarded([&]() -> pcheb_status {
+    Handle& h = *as_handle(hh);
+    check_vectors(h, x, y, nrhs, ld);
+    launch_ahat(h, InVec<double>{x}, EpiStore<double>{y, nullptr, nullptr}, stream);
+    PCHEB_HIP_CHECK(hipGetLastError());
+    return PCHEB_OK;
+  });
+}
+
+pcheb_status pcg_solve(pcheb_handle hh, const double* b, double* x, int32_t nrhs, int64_t ld, double tol,
+                       int32_t maxit, uint32_t flags, pcg_stats* stats, hipStream_t stream) {
+  return guarded([&]() -> pcheb_status {
+    Handle& h = *as_handle(hh);
+    check_vectors(h, b, x, nrhs, ld);
+    if (!(tol > 0.0) || !std::isfinite(tol)) fail(PCHEB_INVALID, "tol must be positive");
+    if (maxit < 1) fail(PCHEB_INVALID, "maxit must be >= 1");
+    pcheb_status st = PCHEB_OK;
+    switch (h.prm.prec) {
+      case PCHEB_F64:
+        st = solve_impl<double>(h, b, x, tol, maxit, flags, stats, stream);
+        break;
+      case PCHEB_F32:
+        st = solve_impl<float>(h, b, x, tol, maxit, flags, stats, stream);
+        break;
+      default:
+        st = solve_impl<bf16>(h, b, x, tol, maxit, flags, stats, stream);
+        break;
+    }
+    if (st == PCHEB_BREAKDOWN) set_last_error("PCG breakdown: (p, Ap) <= 0, (r, z) <= 0 or a non-finite value");
+    if (st == PCHEB_NOT_CONVERGED) set_last_error("PCG reached maxit without meeting tol");
+    return st;
+  });
+}
+
+pcheb_status pcheb_destroy(pcheb_handle hh) {
+  return guarded([&]() -> pcheb_status {
+    if (!hh) return PCHEB_OK;
+    Handle* h = reinterpret_cast<Handle*>(hh);
+    release(*h);
+    delete h;
+    return PCHEB_OK;
+  });
+}
+
+const char* pcheb_last_error(void) { return g_last_error.c_str(); }
+
+size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs) {
+  if (!A || !p) return 0;
+  return footprint(A, p, nrhs);
+}
+
+}  // extern "C"

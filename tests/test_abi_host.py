@@ -1,0 +1,124 @@
+"""The C-ABI library on the host: it loads, exports every declared entry point,
+its structs have the layout the C compiler gives them, and argument checks that
+run before any device work return the documented statuses (no GPU needed)."""
+
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+import paper_2008_01440_amd as pc
+from paper_2008_01440_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcheb.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_abi.library_path()), reason="libpcheb.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    fns = declared_functions()
+    for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
+                 "pcheb_footprint_bytes", "pcheb_estimate_bounds"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.library_path()], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = pc.load_library()
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc missing")
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "pcheb.h"\n'
+        "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f))\n"
+        "int main(void) {\n"
+        ' printf("pcheb_operator %zu\\npcheb_params %zu\\npcg_stats %zu\\n", sizeof(pcheb_operator),'
+        " sizeof(pcheb_params), sizeof(pcg_stats));\n"
+        + "".join(f" O(pcheb_operator, {f});\n" for f, _ in _abi.COperator._fields_)
+        + "".join(f" O(pcheb_params, {f});\n" for f, _ in _abi.CParams._fields_)
+        + "".join(f" O(pcg_stats, {f});\n" for f, _ in _abi.CStats._fields_)
+        + " return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    lines = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True,
+                                                                text=True).stdout.splitlines())
+    for cname, cls in (("pcheb_operator", _abi.COperator), ("pcheb_params", _abi.CParams),
+                       ("pcg_stats", _abi.CStats)):
+        assert int(lines[cname]) == ctypes.sizeof(cls)
+        for f, _ in cls._fields_:
+            assert int(lines[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0):
+    lib = pc.load_library()
+    p = _abi.CParams(k=k, lambda_min=lmin, lambda_max=lmax, theta_scale=s, prec=prec, fuse_steps=1)
+    out = ctypes.c_void_p()
+    return lib.pcheb_setup(ctypes.byref(op.c), ctypes.byref(p), None, ctypes.byref(out))
+
+
+@pytest.mark.parametrize("kw,what", [
+    (dict(k=-1), "degree"), (dict(k=1001), "degree"), (dict(lmin=0.0), "lambda"), (dict(lmin=2.0), "lambda"),
+    (dict(s=0.99), "theta_scale"), (dict(prec=7), "precision"),
+])
+def test_setup_rejects_bad_parameters(kw, what):
+    assert _setup_status(pc.Operator.stencil7(4), **kw) == 1
+    assert what.split("_")[0] in pc.pcheb_last_error()
+
+
+def test_setup_rejects_bad_operators():
+    op = pc.Operator.stencil7(4)
+    op.c.n = 65
+    assert _setup_status(op) == 1 and "nx*ny*nz" in pc.pcheb_last_error()
+    csr = _abi.Operator(_abi.COperator(kind=0, n=10))
+    assert _setup_status(csr) == 1 and "CSR" in pc.pcheb_last_error()
+    sell = _abi.Operator(_abi.COperator(kind=1, n=10, rowptr=8, colind=8, values=8, nnz=10, sell_C=32,
+                                        sell_sigma=1))
+    assert _setup_status(sell) == 1 and "64" in pc.pcheb_last_error()
+    h27 = _abi.Operator(_abi.COperator(kind=3, n=8, nx=2, ny=2, nz=2))
+    assert _setup_status(h27) == 1 and "cell_coeff" in pc.pcheb_last_error()
+    bad = _abi.Operator(_abi.COperator(kind=9, n=8, nx=2, ny=2, nz=2))
+    assert _setup_status(bad) == 1
+
+
+def test_null_arguments():
+    lib = pc.load_library()
+    assert lib.pcheb_setup(None, None, None, None) == 1
+    assert lib.pcheb_apply(None, None, None, 1, 1, None) == 1
+    assert lib.pcg_solve(None, None, None, 1, 1, 1e-8, 10, 0, None, None) == 1
+    assert lib.pcheb_destroy(None) == 0
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    assert lib.pcheb_estimate_bounds(None, None, 30, ctypes.byref(lo), ctypes.byref(hi), None) == 1
+
+
+def test_footprint_scales_with_precision_and_rhs():
+    op = pc.Operator.stencil7(64)
+    f64 = pc.pcheb_footprint_bytes(op, 20, prec="f64")
+    f32 = pc.pcheb_footprint_bytes(op, 20, prec="f32")
+    bf = pc.pcheb_footprint_bytes(op, 20, prec="bf16")
+    assert f64 > f32 > bf > 64 ** 3 * 40
+    assert pc.pcheb_footprint_bytes(op, 20, prec="f32", nrhs=4) > 3 * f32 - 1e6
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "_PKG", str(tmp_path))
+    with pytest.raises(RuntimeError, match="missing"):
+        _abi.load_library()
