@@ -1,0 +1,301 @@
+"""Benchmark: NC-preconditioned PCG solves/s on one MI355X.
+
+Workload (one "step" = one complete pcg_solve): 3-D 7-point Poisson on a 256^3
+grid (16,777,216 unknowns), Dirichlet boundaries, right-hand side b = A x*
+with x* i.i.d. U[-1, 1] (SplitMix64, seed 0), eigenvalue bounds from 30
+Lanczos steps on the GPU with lambda_max widened by 1.01, theta scale
+s = 1.001, tol 1e-8, x0 = 0.  The flagship path is the matrix-free operator
+with the degree-k Chebyshev recurrence in float32 inside a float64 flexible
+PCG.  In the same run it times plain float64 PCG (k = 0, the Jacobi-scaled
+"diagonal preconditioner" baseline of the paper), the float64 NC-PCG and the
+CSR operator, reports the dominant kernel (a middle Chebyshev step) against
+the HBM roofline with HIP events, and times the FP64 CPU oracle on a bounded
+sample of the same workload.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 20] [--prec f32] [--sweep]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG solves/s + P_k(A) HBM GB/s vs FP64 plain PCG; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_stencil7_256_traffic.md")
+KERNEL_SOURCES = ["operators.hpp", "epilogues.hpp", "common.hpp", "dispatch.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2008_01440_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec):
+    """HBM bytes per middle-step launch from the committed rocprofv3 counter summary,
+    or None when it is missing or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.startswith("- "):
+            key, _, v = line[2:].partition(":")
+            vals[key.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(f"traffic_bytes_per_launch_{prec}")
+    return float(v) if v else None
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256, help="grid points per axis")
+    ap.add_argument("--k", type=int, default=20, help="polynomial degree of the flagship solve")
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--fuse", type=int, default=1, help="Chebyshev steps per pass of the matrix-free operator")
+    ap.add_argument("--sweep-fuse", default="1", help="steps per pass tried by the sweep (stencil7 only)")
+    ap.add_argument("--sweep", action="store_true", help="sweep degrees, precisions and operators")
+    ap.add_argument("--sweep-kinds", default="stencil7,csr,sell", help="operators of the sweep")
+    ap.add_argument("--sweep-degrees", default="0,5,10,20,30,50,100", help="degrees of the sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="time the flagship only")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design "
+                                   "is described but not built)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2008_01440_amd as pc
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pc.load_library()
+    n1 = args.n
+    n = n1 ** 3
+
+    t = time.perf_counter()
+    rp, ci, v = W.stencil7_csr(n1)
+    xstar = W.uniform(0, n, -1.0, 1.0)
+    b = W.rhs_from_solution(rp, ci, v, xstar)
+    log(f"inputs: {n1}^3 grid, n={n}, nnz={int(rp[-1])} built in {time.perf_counter() - t:.1f}s")
+    bt = torch.from_numpy(b).to(dev)
+    xs_t = torch.from_numpy(xstar).to(dev)
+    op_st = pc.Operator.stencil7(n1)
+
+    t = time.perf_counter()
+    v0 = torch.from_numpy(W.uniform(7, n, 0.5, 1.5)).to(dev)
+    lo, hi_ritz = pc.pcheb_estimate_bounds(op_st, v0, 30)
+    hi = 1.01 * hi_ritz
+    del v0
+    torch.cuda.synchronize()
+    lanczos_ms = 1e3 * (time.perf_counter() - t)
+    exact_lo, exact_hi = W.stencil7_bounds(n1)
+    log(f"bounds: Lanczos(30) [{lo:.6g}, {hi_ritz:.6g}] x1.01 -> {hi:.6g}  (exact [{exact_lo:.6g}, {exact_hi:.6g}]) "
+        f"in {lanczos_ms:.0f} ms")
+
+    csr_dev = None
+
+    def operator(kind):
+        nonlocal csr_dev
+        if kind == "stencil7":
+            return op_st
+        if csr_dev is None:
+            csr_dev = tuple(torch.from_numpy(a).to(dev) for a in (rp, ci, v))
+        return pc.Operator.csr(*csr_dev, sell=(kind == "sell"), sigma=1)
+
+    def run(kind, k, prec, steps, warmup, flexible=True, time_kernels=False, fuse=1):
+        t0 = time.perf_counter()
+        h = pc.pcheb_setup(operator(kind), k, lo, hi, 1.001, prec, fuse_steps=fuse)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            pc.pcg_solve(h, bt, x, tol=1e-8, maxit=20000, flexible=flexible, time_kernels=time_kernels)
+        torch.cuda.synchronize()
+        lat, stats = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            st = pc.pcg_solve(h, bt, x, tol=1e-8, maxit=20000, flexible=flexible, time_kernels=time_kernels)
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - ts))
+            stats.append(st)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(x - xs_t) / torch.linalg.vector_norm(xs_t))
+        pc.pcheb_destroy(h)
+        st = stats[-1]
+        step_ms = sum(s["step_ms"] for s in stats)
+        step_n = sum(s["step_launches"] for s in stats)
+        res = dict(kind=kind, k=k, prec=prec, fuse=fuse, steps=steps, solves_per_s=steps / total,
+                   ms_per_solve=1e3 * total / steps, p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99),
+                   iters=st["iters"], status=st["status"], relres=st["relres"], relres_true=st["relres_true"],
+                   err_vs_xstar=err, n_spmv=st["n_spmv"], n_dot=st["n_dot"], setup_ms=setup_ms,
+                   step_avg_us=(1e3 * step_ms / step_n) if step_n else None, step_launches=step_n)
+        log(f"  {kind:8s} k={k:3d} {prec:4s} S={fuse}: {res['solves_per_s']:8.3f} solves/s  {res['ms_per_solve']:8.2f} ms  "
+            f"iters={st['iters']:5d} relres_true={st['relres_true']:.2e} err={err:.2e}"
+            + (f"  step {res['step_avg_us']:.1f} us" if step_n else ""))
+        return res
+
+    if args.sweep:
+        rows = []
+        for kind in args.sweep_kinds.split(","):
+            for prec in ("f64", "f32", "bf16"):
+                for k in (int(d) for d in args.sweep_degrees.split(",")):
+                    if k == 0 and prec != "f64":
+                        continue
+                    for fuse in (int(f) for f in args.sweep_fuse.split(",")):
+                        if fuse > 1 and (kind != "stencil7" or k < 3 or (prec == "f64" and fuse > 3)):
+                            continue
+                        rows.append(run(kind, k, prec, 2, 1, time_kernels=k >= 3, fuse=fuse))
+        print(json.dumps({"sweep": rows}))
+        return
+
+    # flagship, timed with the middle Chebyshev steps bracketed by HIP events
+    log("flagship:")
+    flag = run("stencil7", args.k, args.prec, args.steps, args.warmup, time_kernels=True, fuse=args.fuse)
+    variants = {}
+    if not args.no_variants:
+        log("variants:")
+        variants["fp64_plain_pcg"] = run("stencil7", 0, "f64", max(2, args.steps // 4), 1)
+        variants["fp64_nc"] = run("stencil7", args.k, "f64", 2, 1, time_kernels=True, fuse=min(args.fuse, 3))
+        variants["csr_" + args.prec + "_nc"] = run("csr", args.k, args.prec, 2, 1, time_kernels=True)
+
+    # roofline of the dominant kernel.  A middle Chebyshev step reads y_{j-1}, y_{j-2}
+    # and s and writes y_j (the 7-point operator has no stored matrix): 4 e n bytes.
+    # A fused pass of S steps reads the same three vectors and writes two: 5 e n bytes.
+    e = {"f64": 8, "f32": 4, "bf16": 2}[args.prec]
+    S = args.fuse if args.fuse > 1 else 1
+    if S > 1 and (args.k - 2) % S != 0:
+        log(f"note: {args.k - 2} middle steps are not a multiple of {S}; the timed launches mix pass kinds")
+    alg_bytes = (5 if S > 1 else 4) * e * n
+    avg_s = flag["step_avg_us"] * 1e-6 * S
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = measured_traffic(args.prec)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": (f"k_stencil7_fused<S={S},{args.prec}> ({S} middle steps per launch)" if S > 1
+                           else f"k_stencil7<SCALED,EpiChebStep<{args.prec}>> (middle step)"),
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_s * 1e6, 2),
+                "launches_timed": flag["step_launches"] // S,
+                "effective_step_gbs": round(4 * e * n / (flag["step_avg_us"] * 1e-6) / 1e9, 1)}
+
+    ceiling = hbm_triad_ceiling(torch, dev)
+    roofline["measured_triad_ceiling_gbs"] = round(ceiling, 1)
+    roofline["frac_of_triad_ceiling"] = round(achieved / ceiling, 4)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(rp, ci, v, b, lo, hi, args.k, flag["iters"])
+
+    out = {
+        "metric": METRIC,
+        "value": round(flag["solves_per_s"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(flag["ms_per_solve"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "dtype_detail": f"P_k(A) recurrence in {args.prec} storage with "
+                        f"{'f64' if args.prec == 'f64' else 'f32'} arithmetic; outer PCG, dots and residual in f64",
+        "data": "synthetic",
+        "config": {"workload": f"3-D 7-point Poisson {n1}^3 ({n} unknowns), Dirichlet, b = A x*, x* ~ U[-1,1] "
+                               f"seed 0; matrix-free operator; NC degree k={args.k}, theta scale 1.001; bounds "
+                               f"Lanczos(30) with lambda_max x1.01; flexible PCG, tol 1e-8, x0 = 0",
+                   "n": n, "k": args.k, "precision": args.prec, "operator": "stencil7 (matrix-free)",
+                   "steps_per_pass": S,
+                   "lambda_min": lo, "lambda_max": hi},
+        "latency_ms": {"p50": round(flag["p50_ms"], 3), "p99": round(flag["p99_ms"], 3)},
+        "iters": flag["iters"],
+        "relres_true": flag["relres_true"],
+        "err_vs_xstar": flag["err_vs_xstar"],
+        "setup_ms": round(flag["setup_ms"], 2),
+        "lanczos_ms": round(lanczos_ms, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if variants:
+        out["variants"] = {name: {kk: r[kk] for kk in ("kind", "k", "prec", "solves_per_s", "ms_per_solve", "iters",
+                                                       "relres_true", "err_vs_xstar", "step_avg_us")}
+                           for name, r in variants.items()}
+        base = variants["fp64_plain_pcg"]["solves_per_s"]
+        out["speedup_vs_fp64_plain_pcg"] = round(flag["solves_per_s"] / base, 3)
+    print(json.dumps(out))
+
+
+def hbm_triad_ceiling(torch, dev, nbytes=1 << 30, reps=20):
+    """Achievable HBM bandwidth: c = a + 0.5 b on three 1 GiB float64 vectors (12x the
+    256 MB last-level cache), timed with events; 3 GiB moved per pass."""
+    m = nbytes // 8
+    a = torch.ones(m, dtype=torch.float64, device=dev)
+    b = torch.ones(m, dtype=torch.float64, device=dev)
+    c = torch.empty(m, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        torch.add(a, b, alpha=0.5, out=c)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, alpha=0.5, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 3 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    log(f"triad ceiling: {gbs:.0f} GB/s")
+    return gbs
+
+
+def cpu_baseline(rp, ci, v, b, lo, hi, k, gpu_iters):
+    """The FP64 oracle, single-threaded, on a bounded sample: two PCG iterations of the
+    same solve (set-up, 3 preconditioner applications, 2 outer products), scaled to
+    one full solve of gpu_iters iterations by counting operator products."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        res = oracle.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8, maxit=2, flexible=True)
+        dt = time.perf_counter() - t0
+    sample_spmv = res.n_spmv
+    full_spmv = gpu_iters * (k + 1)
+    est_solve_s = dt * full_spmv / sample_spmv
+    log(f"cpu oracle: sample {res.iters} iterations ({sample_spmv} products) in {dt:.1f}s -> "
+        f"{est_solve_s:.1f}s per solve ({full_spmv} products)")
+    return {"value": round(1.0 / est_solve_s, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 numpy/scipy oracle, 1 thread: NC-PCG set-up plus 2 iterations of the same "
+                      f"{len(rp) - 1}-unknown solve (k={k}; {sample_spmv} operator products) in {dt:.2f} s, "
+                      f"scaled by operator products to the GPU's {gpu_iters}-iteration solve"}
+
+
+if __name__ == "__main__":
+    main()

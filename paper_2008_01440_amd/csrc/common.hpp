@@ -1,6 +1,6 @@
 // Device-side building blocks shared by every kernel of the library:
 // storage types (float64 / float32 / bfloat16 with float32 arithmetic),
-// wavefront and block sums, the single-pass grid reduction, XCD-aware tile
+// wavefront and block sums, the two-kernel grid reduction, XCD-aware tile
 // enumeration and the solver state that lives in device memory.
 #pragma once
 
@@ -34,11 +34,16 @@ __device__ __forceinline__ uint16_t float_to_bf16(float f) {
 template <class T>
 struct Store;
 
+// ld/st: one element; st2: elements i and i+1 in one access (i even, base
+// pointer aligned to the pair size).
 template <>
 struct Store<double> {
   using acc = double;
   static __device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; }
   static __device__ __forceinline__ void st(double* p, int64_t i, double v) { p[i] = v; }
+  static __device__ __forceinline__ void st2(double* p, int64_t i, double a, double b) {
+    *reinterpret_cast<double2*>(p + i) = make_double2(a, b);
+  }
 };
 
 template <>
@@ -46,6 +51,9 @@ struct Store<float> {
   using acc = float;
   static __device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
   static __device__ __forceinline__ void st(float* p, int64_t i, float v) { p[i] = v; }
+  static __device__ __forceinline__ void st2(float* p, int64_t i, float a, float b) {
+    *reinterpret_cast<float2*>(p + i) = make_float2(a, b);
+  }
 };
 
 template <>
@@ -53,13 +61,18 @@ struct Store<bf16> {
   using acc = float;
   static __device__ __forceinline__ float ld(const bf16* p, int64_t i) { return bf16_to_float(p[i].bits); }
   static __device__ __forceinline__ void st(bf16* p, int64_t i, float v) { p[i].bits = float_to_bf16(v); }
+  static __device__ __forceinline__ void st2(bf16* p, int64_t i, float a, float b) {
+    *reinterpret_cast<uint32_t*>(p + i) = uint32_t(float_to_bf16(a)) | (uint32_t(float_to_bf16(b)) << 16);
+  }
 };
+
+__device__ __forceinline__ double2 ld2(const double* p, int64_t i) { return *reinterpret_cast<const double2*>(p + i); }
 
 // ---------------------------------------------------------------- solver state
 
 // Scalars of one PCG solve.  They stay in device memory: kernels read alpha
-// and beta from here and the last block of each reduction writes them, so the
-// host never sits between two iterations.
+// and beta from here and the finalize kernel of each reduction writes them, so
+// the host never sits between two iterations.
 struct DevState {
   double gamma;      // (r, z) for the current z
   double alpha;      // gamma / (p, q)
@@ -83,11 +96,9 @@ struct DevState {
 
 enum : int32_t { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIter = 3 };
 
-// Partial sums of a grid reduction: one slot of kMaxReduce doubles per block
-// plus an arrival counter that the last block resets to zero.
+// Partial sums of a grid reduction: one slot of kMaxReduce doubles per block.
 struct ReduceBuf {
   double* partials;
-  unsigned int* counter;
 };
 
 // ---------------------------------------------------------------- reductions
@@ -123,43 +134,36 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
   __syncthreads();
 }
 
-__device__ __forceinline__ double load_l2(const double* p) {
-  // read past the per-CU vector cache: partial sums were written by other CUs
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Single-pass grid reduction.  Every block sums its values and stores them in
-// its own slot; the block that arrives last adds all slots in slot order (a
-// fixed order, so the result is reproducible for a given grid) and calls
-// fin(total) from thread 0.  All threads of every block must call it.
-template <int NV, class Fin>
-__device__ __forceinline__ void grid_reduce(double (&v)[NV], ReduceBuf rb, Fin fin) {
+// Grid reductions in two kernels.  Every block of the producing kernel sums
+// its values and stores them, with a plain store, in its own slot; a one-block
+// finalize kernel then adds the slots in slot order (a fixed order, so the
+// result is reproducible for a given grid) and calls fin(total).  The kernel
+// boundary makes the slots visible, so no block needs a device-scope fence
+// (on a multi-XCD part such a fence writes back and invalidates the whole
+// L2 of the die) and no atomic counter is contended.
+template <int NV>
+__device__ __forceinline__ void block_partial(double (&v)[NV], ReduceBuf rb) {
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-  const unsigned nb = gridDim.x;
-  __shared__ unsigned int is_last;
   block_sum<NV>(v, tid);
   if (tid == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) rb.partials[size_t(blockIdx.x) * kMaxReduce + i] = v[i];
-    __threadfence();
-    const unsigned int ticket = atomicAdd(rb.counter, 1u);
-    is_last = (ticket == nb - 1) ? 1u : 0u;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+template <int NV, class Fin>
+__global__ __launch_bounds__(kBlock) void k_finalize(Fin fin, ReduceBuf rb, uint32_t nblocks,
+                                                     const DevState* guard) {
+  if (guard && guard->done != kRunning) return;
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (unsigned b = tid; b < nb; b += kBlock) {
+  for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += load_l2(rb.partials + size_t(b) * kMaxReduce + i);
+    for (int i = 0; i < NV; ++i) acc[i] += rb.partials[size_t(b) * kMaxReduce + i];
   }
-  block_sum<NV>(acc, tid);
-  if (tid == 0) {
-    *rb.counter = 0u;
-    fin(acc);
-  }
+  block_sum<NV>(acc, threadIdx.x);
+  if (threadIdx.x == 0) fin(acc);
 }
 
 // ---------------------------------------------------------------- tile enumeration

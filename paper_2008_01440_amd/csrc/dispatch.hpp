@@ -30,29 +30,32 @@ template <bool SCALED, class Tv, class In, class Epi>
 void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Epi epi, hipStream_t s) {
   using acc = typename Epi::acc;
   const pcheb_operator& op = h.op;
+  uint32_t grid = 0;
   switch (op.kind) {
     case PCHEB_OP_STENCIL7: {
       const StencilGrid g = stencil_grid(op);
-      k_stencil7<SCALED, kZChunk, In, Epi><<<g.grid, dim3(64, 4), 0, s>>>(in, epi, op.nx, op.ny, op.nz, g.tiles_x,
-                                                                        g.tiles_y, g.ntiles, h.rb());
+      grid = g.grid;
+      k_stencil7<SCALED, kZChunk, In, Epi><<<grid, dim3(64, 4), 0, s>>>(in, epi, op.nx, op.ny, op.nz, g.tiles_x,
+                                                                      g.tiles_y, g.ntiles, h.rb());
       break;
     }
     case PCHEB_OP_STENCIL27H: {
       const StencilGrid g = stencil_grid(op);
+      grid = g.grid;
       const acc* kappa = nullptr;
       if constexpr (sizeof(acc) == 8) {
         kappa = reinterpret_cast<const acc*>(op.cell_coeff);
       } else {
         kappa = reinterpret_cast<const acc*>(h.kappa_lo);
       }
-      k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<g.grid, dim3(64, 4), 0, s>>>(
+      k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<grid, dim3(64, 4), 0, s>>>(
           in, epi, kappa, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb());
       break;
     }
     case PCHEB_OP_CSR: {
       const int rows = kBlock / h.lanes;
       const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);
-      const uint32_t grid = round_grid(tiles);
+      grid = round_grid(tiles);
 #define PCHEB_CSR_CASE(L)                                                                              \
   case L:                                                                                              \
     k_csr<L, Tv, In, Epi><<<grid, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n, uint32_t(tiles), \
@@ -71,13 +74,16 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     }
     case PCHEB_OP_SELL: {
       const uint64_t tiles = uint64_t((h.nchunks + 3) / 4);
-      const uint32_t grid = round_grid(tiles);
+      grid = round_grid(tiles);
       k_sell<Tv, In, Epi><<<grid, kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val, h.sell_perm, in, epi,
                                                   h.n, uint32_t(tiles), h.rb());
       break;
     }
     default:
       fail(PCHEB_INVALID, "unknown operator kind");
+  }
+  if constexpr (Epi::reduce) {
+    k_finalize<Epi::NV, EpiFin<Epi>><<<1, kBlock, 0, s>>>(EpiFin<Epi>{epi}, h.rb(), grid, epi.guard);
   }
 }
 

@@ -57,7 +57,9 @@ struct Handle {
 
   // workspace for one right-hand side
   void* s = nullptr;          // D^-1 r (storage precision)
-  void* Y[3] = {nullptr, nullptr, nullptr};  // recurrence iterates (storage precision)
+  void* Y[4] = {nullptr, nullptr, nullptr, nullptr};  // recurrence iterates (storage precision)
+  int nY = 3;                 // iterate buffers in use (4 when steps are fused)
+  int fuse = 1;               // recurrence steps per pass (7-point stencil only)
   double* r = nullptr;
   double* p[2] = {nullptr, nullptr};
   double* q = nullptr;
@@ -65,7 +67,6 @@ struct Handle {
   DevState* st = nullptr;     // device scalars of the current solve
   DevState* st_host = nullptr;  // pinned host mirror (two slots)
   double* partials = nullptr;
-  unsigned int* counter = nullptr;
 
   // graph cache for the PCG iteration pair (captured on a private stream,
   // launched on the caller's; the legacy null stream cannot be captured)
@@ -77,7 +78,7 @@ struct Handle {
   std::vector<hipEvent_t> events;
   std::vector<DeviceBuffer> owned;
 
-  ReduceBuf rb() const { return ReduceBuf{partials, counter}; }
+  ReduceBuf rb() const { return ReduceBuf{partials}; }
 };
 
 void* dev_alloc(Handle& h, size_t bytes);

@@ -13,7 +13,7 @@
 //        DevState* st (may be null; written by fin); const DevState* guard (may be
 //        null; the kernel does nothing once guard->done is set); __device__ void prepare();
 //        __device__ void operator()(int64_t i, acc yi, acc mi, double (&part)[NV]) const;
-//        __device__ void fin(double (&total)[NV]) const;   // thread 0 of the last block
+//        __device__ void fin(double (&total)[NV]) const;   // thread 0 of the finalize kernel
 //
 // M is A_hat (SCALED = false) or D^-1 A_hat (SCALED = true); for CSR and
 // SELL it is whatever value array the caller passes.
@@ -29,11 +29,16 @@ __device__ __forceinline__ bool solve_finished(const Epi& epi) {
 }
 
 template <class Epi>
-__device__ __forceinline__ void finish_reduction(const Epi& epi, double (&part)[Epi::NV], ReduceBuf rb) {
-  if constexpr (Epi::reduce) {
-    grid_reduce<Epi::NV>(part, rb, [&](double (&t)[Epi::NV]) { epi.fin(t); });
-  }
+__device__ __forceinline__ void finish_reduction(const Epi&, double (&part)[Epi::NV], ReduceBuf rb) {
+  if constexpr (Epi::reduce) block_partial<Epi::NV>(part, rb);
 }
+
+// Calls epi.fin(total) from the finalize kernel.
+template <class Epi>
+struct EpiFin {
+  Epi epi;
+  __device__ __forceinline__ void operator()(double (&t)[Epi::NV]) const { epi.fin(t); }
+};
 
 // ------------------------------------------------------------------ 7-point stencil
 //

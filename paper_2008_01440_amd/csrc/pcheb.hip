@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "dispatch.hpp"
+#include "fused_stencil.hpp"
 #include "handle.hpp"
 
 namespace pcheb {
@@ -166,90 +167,43 @@ __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
   }
 }
 
-// x0 = 0: x = 0, r = b, p_old = 0 and the norms of b.
-__global__ void k_start_zero(const double* b, double* x, double* r, double* p_old, InvDiag invd, int64_t n,
-                             DevState* st, ReduceBuf rb) {
-  double part[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    const double bi = b[i];
-    x[i] = 0.0;
-    r[i] = bi;
-    p_old[i] = 0.0;
-    part[0] += bi * bi * invd(i);
-    part[1] += bi * bi;
-  }
-  grid_reduce<2>(part, rb, [&](double (&t)[2]) {
+// Elementwise kernels walk the vectors in pairs of elements (16-byte float64
+// accesses; every vector is 16-byte aligned), with a scalar tail for odd n.
+#define PAIR_STRIDE(i, n)                                                                  \
+  for (int64_t i = 2 * (int64_t(blockIdx.x) * blockDim.x + threadIdx.x); i < (n);           \
+       i += 2 * int64_t(gridDim.x) * blockDim.x)
+
+static uint32_t pair_grid(int64_t n) { return flat_grid((n + 1) / 2); }
+
+__device__ __forceinline__ double2 invd2(InvDiag d, int64_t i) {
+  return d.p ? ld2(d.p, i) : make_double2(d.c, d.c);
+}
+
+struct FinStart {
+  DevState* st;
+  __device__ void operator()(double (&t)[2]) const {
     st->bb = t[0];
     st->rr = t[0];
     st->bb_hat = t[1];
     st->relres = t[0] > 0.0 ? 1.0 : 0.0;
     if (!(t[0] > 0.0)) st->done = isfinite(t[0]) ? kConverged : kBreakdown;
-  });
-}
+  }
+};
 
-// Preconditioner input: s = D^-1 r and y_0 = s / theta' in the storage precision.
-template <class T>
-__global__ void k_prep(const double* r, T* s, T* y0, InvDiag invd, double inv_theta, int64_t n,
-                       const DevState* guard) {
-  if (guard && guard->done != kRunning) return;
-  GRID_STRIDE(i, n) {
-    const double si = r[i] * invd(i);
-    Store<T>::st(s, i, typename Store<T>::acc(si));
-    Store<T>::st(y0, i, typename Store<T>::acc(si * inv_theta));
+struct FinBeta {
+  DevState* st;
+  int init, flexible;
+  __device__ void operator()(double (&t)[2]) const {
+    EpiChebLast<double, true, true>::finish_beta(st, t[0], t[1], init, flexible);
   }
-}
+};
 
-// Degree 0: z = D^-1 r / theta' (the diagonal preconditioner), optionally with
-// the dot products and beta of the last recurrence step.
-__global__ void k_jacobi(const double* r, double* z, const double* q, InvDiag invd, double inv_theta, int64_t n,
-                         DevState* st, const DevState* guard, ReduceBuf rb, int dots, int init, int flexible) {
-  if (guard && guard->done != kRunning) return;
-  double part[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    const double ri = r[i];
-    const double zi = ri * invd(i) * inv_theta;
-    z[i] = zi;
-    part[0] += ri * zi;
-    if (flexible) part[1] += zi * q[i];
-  }
-  if (dots) {
-    grid_reduce<2>(part, rb, [&](double (&t)[2]) {
-      EpiChebLast<double, true, true>::finish_beta(st, t[0], t[1], init, flexible);
-    });
-  }
-}
-
-// Iteration update x += alpha p, r -= alpha q with ||r||^2 (D^-1 weighted), the
-// stop test on the device, and the next preconditioner input fused in:
-//   MODE 0 (k >= 1): s = D^-1 r, y_0 = s / theta';
-//   MODE 1 (k = 0):  z = D^-1 r / theta' with (r, z), (z, q) and beta;
-//   MODE 2:          nothing else (the residual is refreshed before the next step).
-template <class T, int MODE>
-__global__ void k_update(double* x, double* r, const double* p, const double* q, InvDiag invd, T* s, T* y0,
-                         double* z, double inv_theta, int64_t n, DevState* st, ReduceBuf rb) {
-  if (st->done != kRunning) return;
-  const double alpha = st->alpha;
-  const int flexible = st->flexible;
-  double part[3] = {0.0, 0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    const double qi = q[i];
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * qi;
-    r[i] = ri;
-    const double w = invd(i);
-    part[0] += ri * ri * w;
-    if (MODE == 0) {
-      const double si = ri * w;
-      Store<T>::st(s, i, typename Store<T>::acc(si));
-      Store<T>::st(y0, i, typename Store<T>::acc(si * inv_theta));
-    } else if (MODE == 1) {
-      const double zi = ri * w * inv_theta;
-      z[i] = zi;
-      part[1] += ri * zi;
-      if (flexible) part[2] += zi * qi;
-    }
-  }
-  grid_reduce<3>(part, rb, [&](double (&t)[3]) {
+// Stop test after the update: iteration count, relative residual, limits, and
+// (MODE 1, degree 0) beta from the fused dot products.
+template <int MODE>
+struct FinUpdate {
+  DevState* st;
+  __device__ void operator()(double (&t)[3]) const {
     st->rr = t[0];
     st->iter += 1;
     st->relres = sqrt(t[0]) / sqrt(st->bb);
@@ -260,9 +214,133 @@ __global__ void k_update(double* x, double* r, const double* p, const double* q,
     } else if (st->iter >= st->maxit) {
       st->done = kMaxIter;
     } else if (MODE == 1) {
-      EpiChebLast<double, true, true>::finish_beta(st, t[1], t[2], 0, flexible);
+      EpiChebLast<double, true, true>::finish_beta(st, t[1], t[2], 0, st->flexible);
     }
-  });
+  }
+};
+
+// x0 = 0: x = 0, r = b, p_old = 0 and the norms of b.
+__global__ void k_start_zero(const double* b, double* x, double* r, double* p_old, InvDiag invd, int64_t n,
+                             ReduceBuf rb) {
+  double part[2] = {0.0, 0.0};
+  PAIR_STRIDE(i, n) {
+    if (i + 1 < n) {
+      const double2 bv = ld2(b, i), w = invd2(invd, i);
+      *reinterpret_cast<double2*>(x + i) = make_double2(0.0, 0.0);
+      *reinterpret_cast<double2*>(r + i) = bv;
+      *reinterpret_cast<double2*>(p_old + i) = make_double2(0.0, 0.0);
+      part[0] += bv.x * bv.x * w.x + bv.y * bv.y * w.y;
+      part[1] += bv.x * bv.x + bv.y * bv.y;
+    } else {
+      const double bi = b[i];
+      x[i] = 0.0;
+      r[i] = bi;
+      p_old[i] = 0.0;
+      part[0] += bi * bi * invd(i);
+      part[1] += bi * bi;
+    }
+  }
+  block_partial<2>(part, rb);
+}
+
+// Preconditioner input: s = D^-1 r and y_0 = s / theta' in the storage precision.
+template <class T>
+__global__ void k_prep(const double* r, T* s, T* y0, InvDiag invd, double inv_theta, int64_t n,
+                       const DevState* guard) {
+  if (guard && guard->done != kRunning) return;
+  using acc = typename Store<T>::acc;
+  PAIR_STRIDE(i, n) {
+    if (i + 1 < n) {
+      const double2 rv = ld2(r, i), w = invd2(invd, i);
+      const double s0 = rv.x * w.x, s1 = rv.y * w.y;
+      Store<T>::st2(s, i, acc(s0), acc(s1));
+      Store<T>::st2(y0, i, acc(s0 * inv_theta), acc(s1 * inv_theta));
+    } else {
+      const double si = r[i] * invd(i);
+      Store<T>::st(s, i, acc(si));
+      Store<T>::st(y0, i, acc(si * inv_theta));
+    }
+  }
+}
+
+// Degree 0: z = D^-1 r / theta' (the diagonal preconditioner), optionally with
+// the dot products (r, z), (z, q) whose finalize forms beta.
+__global__ void k_jacobi(const double* r, double* z, const double* q, InvDiag invd, double inv_theta, int64_t n,
+                         const DevState* guard, ReduceBuf rb, int dots, int flexible) {
+  if (guard && guard->done != kRunning) return;
+  double part[2] = {0.0, 0.0};
+  PAIR_STRIDE(i, n) {
+    if (i + 1 < n) {
+      const double2 rv = ld2(r, i), w = invd2(invd, i);
+      const double z0 = rv.x * w.x * inv_theta, z1 = rv.y * w.y * inv_theta;
+      *reinterpret_cast<double2*>(z + i) = make_double2(z0, z1);
+      part[0] += rv.x * z0 + rv.y * z1;
+      if (flexible) {
+        const double2 qv = ld2(q, i);
+        part[1] += z0 * qv.x + z1 * qv.y;
+      }
+    } else {
+      const double ri = r[i];
+      const double zi = ri * invd(i) * inv_theta;
+      z[i] = zi;
+      part[0] += ri * zi;
+      if (flexible) part[1] += zi * q[i];
+    }
+  }
+  if (dots) block_partial<2>(part, rb);
+}
+
+// Iteration update x += alpha p, r -= alpha q with ||r||^2 (D^-1 weighted), and
+// the next preconditioner input fused in:
+//   MODE 0 (k >= 1): s = D^-1 r, y_0 = s / theta';
+//   MODE 1 (k = 0):  z = D^-1 r / theta' with (r, z), (z, q);
+//   MODE 2:          nothing else (the residual is refreshed before the next step).
+// The stop test runs in the finalize kernel (FinUpdate).
+template <class T, int MODE>
+__global__ void k_update(double* x, double* r, const double* p, const double* q, InvDiag invd, T* s, T* y0,
+                         double* z, double inv_theta, int64_t n, const DevState* st, ReduceBuf rb) {
+  if (st->done != kRunning) return;
+  using acc = typename Store<T>::acc;
+  const double alpha = st->alpha;
+  const int flexible = st->flexible;
+  double part[3] = {0.0, 0.0, 0.0};
+  PAIR_STRIDE(i, n) {
+    if (i + 1 < n) {
+      const double2 xv = ld2(x, i), pv = ld2(p, i), rv = ld2(r, i), qv = ld2(q, i), w = invd2(invd, i);
+      *reinterpret_cast<double2*>(x + i) = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+      const double r0 = rv.x - alpha * qv.x, r1 = rv.y - alpha * qv.y;
+      *reinterpret_cast<double2*>(r + i) = make_double2(r0, r1);
+      part[0] += r0 * r0 * w.x + r1 * r1 * w.y;
+      if (MODE == 0) {
+        const double s0 = r0 * w.x, s1 = r1 * w.y;
+        Store<T>::st2(s, i, acc(s0), acc(s1));
+        Store<T>::st2(y0, i, acc(s0 * inv_theta), acc(s1 * inv_theta));
+      } else if (MODE == 1) {
+        const double z0 = r0 * w.x * inv_theta, z1 = r1 * w.y * inv_theta;
+        *reinterpret_cast<double2*>(z + i) = make_double2(z0, z1);
+        part[1] += r0 * z0 + r1 * z1;
+        if (flexible) part[2] += z0 * qv.x + z1 * qv.y;
+      }
+    } else {
+      const double qi = q[i];
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * qi;
+      r[i] = ri;
+      const double w = invd(i);
+      part[0] += ri * ri * w;
+      if (MODE == 0) {
+        const double si = ri * w;
+        Store<T>::st(s, i, acc(si));
+        Store<T>::st(y0, i, acc(si * inv_theta));
+      } else if (MODE == 1) {
+        const double zi = ri * w * inv_theta;
+        z[i] = zi;
+        part[1] += ri * zi;
+        if (flexible) part[2] += zi * qi;
+      }
+    }
+  }
+  block_partial<3>(part, rb);
 }
 
 // ================================================================ preconditioner
@@ -299,26 +377,76 @@ struct StepTimer {
   }
 };
 
+// ---- fused passes (7-point stencil): S middle steps per launch
+
+template <class T, int S, int TY>
+static void launch_fused(const Handle& h, const T* ya, const T* yb, T* oa, T* ob, int j, const DevState* guard,
+                         hipStream_t s) {
+  FusedCoef<typename Store<T>::acc, S> cf;
+  for (int m = 0; m < S; ++m) {
+    const Coef<T> c = step_coef<T>(h, j + m);
+    cf.a[m] = c.a;
+    cf.b[m] = c.b;
+    cf.c[m] = c.c;
+  }
+  const pcheb_operator& op = h.op;
+  const uint32_t tiles_x = uint32_t((op.nx + 63) / 64), tiles_y = uint32_t((op.ny + TY - 1) / TY);
+  const uint32_t xy = tiles_x * tiles_y;
+  // about 1024 tiles (four per CU), each z range at least 4 S planes deep
+  const int max_chunks = std::max(1, op.nz / (4 * S));
+  const int chunks = std::max(1, std::min<int>(max_chunks, int((1024 + xy - 1) / xy)));
+  const int zc = (op.nz + chunks - 1) / chunks;
+  const uint32_t ntiles = xy * uint32_t((op.nz + zc - 1) / zc);
+  k_stencil7_fused<S, TY, T><<<round_grid(ntiles), kBlock, 0, s>>>(
+      ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard);
+}
+
+template <class T>
+static void launch_fused_any(const Handle& h, int S, const T* ya, const T* yb, T* oa, T* ob, int j,
+                             const DevState* guard, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (S == 2)
+      launch_fused<T, 2, 8>(h, ya, yb, oa, ob, j, guard, s);
+    else
+      launch_fused<T, 3, 4>(h, ya, yb, oa, ob, j, guard, s);
+  } else {
+    if (S == 2)
+      launch_fused<T, 2, 8>(h, ya, yb, oa, ob, j, guard, s);
+    else if (S == 3)
+      launch_fused<T, 3, 8>(h, ya, yb, oa, ob, j, guard, s);
+    else
+      launch_fused<T, 4, 8>(h, ya, yb, oa, ob, j, guard, s);
+  }
+}
+
+// Steps per pass: fusion applies to the 7-point operator with four iterate buffers.
+static int effective_fuse(const Handle& h) {
+  return (h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2 && h.nY >= 4) ? h.fuse : 1;
+}
+
 // Steps 1..k of Alg. 2 on the prepared input (s, y_0 = Y[0]); the last step
-// writes z in float64.  dots: reduce (r, z), (z, q) and form beta (inside a solve).
+// writes z in float64.  dots: reduce (r, z), (z, q) and form beta (inside a
+// solve).  Middle steps run S at a time when fusion is on.
 template <class T>
 static void enqueue_steps(Handle& h, double* z, const double* r, const double* q, bool dots, int init, int flexible,
                           DevState* guard, StepTimer* timer, hipStream_t s) {
   const int k = h.prm.k;
-  T* Y[3] = {reinterpret_cast<T*>(h.Y[0]), reinterpret_cast<T*>(h.Y[1]), reinterpret_cast<T*>(h.Y[2])};
+  const int S = effective_fuse(h);
+  T* Y[4] = {reinterpret_cast<T*>(h.Y[0]), reinterpret_cast<T*>(h.Y[1]), reinterpret_cast<T*>(h.Y[2]),
+             reinterpret_cast<T*>(h.Y[3])};
   const T* sv = reinterpret_cast<const T*>(h.s);
-  for (int j = 1; j <= k; ++j) {
+  int cur = 0, prev = -1;  // buffers holding y_{j-1} and y_{j-2}
+  auto free_buf = [&](int also_avoid) {
+    for (int i = 0; i < h.nY; ++i)
+      if (i != cur && i != prev && i != also_avoid) return i;
+    return -1;
+  };
+  for (int j = 1; j <= k;) {
     if (timer && k >= 3 && j == 2) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
-    const Coef<T> c = step_coef<T>(h, j);
-    const T* yin = Y[(j - 1) % 3];
-    const T* yprev = j >= 2 ? Y[(j - 2) % 3] : nullptr;
-    if (j < k) {
-      T* yout = Y[j % 3];
-      if (j == 1)
-        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, true>{yprev, sv, yout, c.a, c.b, c.c, nullptr, guard}, s);
-      else
-        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, false>{yprev, sv, yout, c.a, c.b, c.c, nullptr, guard}, s);
-    } else {
+    const T* yin = Y[cur];
+    const T* yprev = prev >= 0 ? Y[prev] : nullptr;
+    if (j == k) {
+      const Coef<T> c = step_coef<T>(h, j);
       if (j == 1) {
         if (dots)
           launch_bop<T>(h, InVec<T>{yin},
@@ -334,8 +462,27 @@ static void enqueue_steps(Handle& h, double* z, const double* r, const double* q
           launch_bop<T>(h, InVec<T>{yin},
                         EpiChebLast<T, false, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0}, s);
       }
+      break;
     }
-    if (timer && k >= 3 && j == k - 1) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
+    if (j >= 2 && S >= 2 && j + S - 1 <= k - 1) {
+      const int ob = free_buf(-1);
+      const int oa = free_buf(ob);
+      launch_fused_any<T>(h, S, yin, yprev, Y[oa], Y[ob], j, guard, s);
+      prev = ob;
+      cur = oa;
+      j += S;
+    } else {
+      const int o = free_buf(-1);
+      const Coef<T> c = step_coef<T>(h, j);
+      if (j == 1)
+        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, true>{yprev, sv, Y[o], c.a, c.b, c.c, nullptr, guard}, s);
+      else
+        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, false>{yprev, sv, Y[o], c.a, c.b, c.c, nullptr, guard}, s);
+      prev = cur;
+      cur = o;
+      ++j;
+    }
+    if (timer && k >= 3 && j == k) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
   }
 }
 
@@ -343,11 +490,10 @@ template <class T>
 static void enqueue_apply(Handle& h, const double* r, double* z, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
-    k_jacobi<<<flat_grid(n), kBlock, 0, s>>>(r, z, nullptr, invdiag(h), 1.0 / h.theta, n, h.st, nullptr, h.rb(), 0, 0,
-                                             0);
+    k_jacobi<<<pair_grid(n), kBlock, 0, s>>>(r, z, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr, h.rb(), 0, 0);
     return;
   }
-  k_prep<T><<<flat_grid(n), kBlock, 0, s>>>(r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
+  k_prep<T><<<pair_grid(n), kBlock, 0, s>>>(r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
                                            1.0 / h.theta, n, nullptr);
   enqueue_steps<T>(h, z, r, nullptr, false, 0, 0, nullptr, nullptr, s);
 }
@@ -514,8 +660,10 @@ static void setup_preconditioner(Handle& h, hipStream_t s) {
   h.elem = storage_bytes(h.prm.prec);
   PCHEB_BY_PREC(h, build_scaled_values, h, s);
 
+  h.fuse = std::max(1, std::min(h.prm.fuse_steps, h.prm.prec == PCHEB_F64 ? 3 : 4));
+  h.nY = (h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2) ? 4 : 3;
   h.s = dev_alloc(h, size_t(n) * h.elem);
-  for (auto& y : h.Y) y = dev_alloc(h, size_t(n) * h.elem);
+  for (int i = 0; i < h.nY; ++i) h.Y[i] = dev_alloc(h, size_t(n) * h.elem);
   h.r = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
   h.p[0] = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
   h.p[1] = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
@@ -523,8 +671,6 @@ static void setup_preconditioner(Handle& h, hipStream_t s) {
   h.z = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
   h.st = static_cast<DevState*>(dev_alloc(h, sizeof(DevState)));
   h.partials = static_cast<double*>(dev_alloc(h, size_t(kMaxGrid) * kMaxReduce * sizeof(double)));
-  h.counter = static_cast<unsigned int*>(dev_alloc(h, sizeof(unsigned int)));
-  PCHEB_HIP_CHECK(hipMemsetAsync(h.counter, 0, sizeof(unsigned int), s));
   PCHEB_HIP_CHECK(hipMemsetAsync(h.st, 0, sizeof(DevState), s));
   PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h.st_host), 2 * sizeof(DevState), hipHostMallocDefault));
   std::memset(h.st_host, 0, 2 * sizeof(DevState));
@@ -542,7 +688,8 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
     if (A->sell_sigma > 1) b += size_t(n) * 4;
   }
   if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 4 : 0);
-  const size_t per_rhs = size_t(n) * (4 * e + 5 * 8);
+  const int ny = (A->kind == PCHEB_OP_STENCIL7 && p->fuse_steps >= 2) ? 4 : 3;
+  const size_t per_rhs = size_t(n) * ((1 + ny) * e + 5 * 8);
   b += size_t(std::max(1, nrhs)) * per_rhs;
   b += size_t(kMaxGrid) * kMaxReduce * 8 + sizeof(DevState) + 256;
   return b;
@@ -554,11 +701,12 @@ template <class T>
 static void enqueue_prep_or_jacobi(Handle& h, int init, int flexible, StepTimer* timer, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
-    k_jacobi<<<flat_grid(n), kBlock, 0, s>>>(h.r, h.z, h.q, invdiag(h), 1.0 / h.theta, n, h.st, h.st, h.rb(), 1, init,
-                                             flexible);
+    const uint32_t g = pair_grid(n);
+    k_jacobi<<<g, kBlock, 0, s>>>(h.r, h.z, h.q, invdiag(h), 1.0 / h.theta, n, h.st, h.rb(), 1, flexible);
+    k_finalize<2, FinBeta><<<1, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st);
     return;
   }
-  k_prep<T><<<flat_grid(n), kBlock, 0, s>>>(h.r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
+  k_prep<T><<<pair_grid(n), kBlock, 0, s>>>(h.r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
                                            1.0 / h.theta, n, h.st);
   enqueue_steps<T>(h, h.z, h.r, h.q, true, init, flexible, h.st, timer, s);
 }
@@ -572,10 +720,11 @@ static void enqueue_iteration(Handle& h, double* x, const double* b, int cur, in
   DevState* st = h.st;
   double* p_new = h.p[cur ^ 1];
   launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0}, EpiDirection{p_new, h.q, st, st}, s);
-  const uint32_t g = flat_grid(n);
+  const uint32_t g = pair_grid(n);
   if (refresh) {
     k_update<T, 2><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), nullptr, nullptr, nullptr, 0.0, n, st,
                                         h.rb());
+    k_finalize<3, FinUpdate<2>><<<1, kBlock, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st);
     launch_ahat(h, InVec<double>{x}, EpiResidual{b, h.r, invdiag(h), st, st, 2}, s);
     enqueue_prep_or_jacobi<T>(h, 0, flexible, timer, s);
     return;
@@ -583,9 +732,11 @@ static void enqueue_iteration(Handle& h, double* x, const double* b, int cur, in
   if (h.prm.k == 0) {
     k_update<double, 1><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), nullptr, nullptr, h.z, 1.0 / h.theta, n,
                                              st, h.rb());
+    k_finalize<3, FinUpdate<1>><<<1, kBlock, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st);
   } else {
     k_update<T, 0><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), reinterpret_cast<T*>(h.s),
                                         reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb());
+    k_finalize<3, FinUpdate<0>><<<1, kBlock, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st);
     enqueue_steps<T>(h, h.z, h.r, h.q, true, 0, flexible, st, timer, s);
   }
 }
@@ -636,7 +787,9 @@ static pcheb_status solve_impl(Handle& h, const double* b, double* x, double tol
     k_fill<<<flat_grid(n), kBlock, 0, s>>>(h.p[0], n, 0.0);
     launch_ahat(h, InVec<double>{x}, EpiResidual{b, h.r, invdiag(h), h.st, nullptr, 0}, s);
   } else {
-    k_start_zero<<<flat_grid(n), kBlock, 0, s>>>(b, x, h.r, h.p[0], invdiag(h), n, h.st, h.rb());
+    const uint32_t g = pair_grid(n);
+    k_start_zero<<<g, kBlock, 0, s>>>(b, x, h.r, h.p[0], invdiag(h), n, h.rb());
+    k_finalize<2, FinStart><<<1, kBlock, 0, s>>>(FinStart{h.st}, h.rb(), g, nullptr);
   }
   enqueue_prep_or_jacobi<T>(h, 1, flexible, tp, s);
   PCHEB_HIP_CHECK(hipGetLastError());
@@ -789,6 +942,8 @@ static void check_vectors(const Handle& h, const void* a, const void* b, int32_t
   if (!a || !b) fail(PCHEB_INVALID, "null vector");
   if (nrhs != 1) fail(PCHEB_INVALID, "this build supports nrhs = 1");
   if (ld < h.n) fail(PCHEB_INVALID, "ld must be >= n");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) % 16 != 0)
+    fail(PCHEB_INVALID, "vectors must be 16-byte aligned");
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
   const size_t bytes = size_t(h.n) * 8;

@@ -249,3 +249,46 @@ def test_residual_refresh_keeps_convergence(pc):
             res.append(st)
     assert res[0]["iters"] > 50
     assert abs(res[0]["iters"] - res[1]["iters"]) <= 2 and res[1]["relres_true"] <= TRUE_RES
+
+
+FUSED_DIMS = [(67, 13, 19), (130, 33, 40), (64, 8, 16)]
+
+
+@pytest.mark.parametrize("prec,S", [("f64", 2), ("f64", 3), ("f32", 2), ("f32", 3), ("f32", 4),
+                                    ("bf16", 2), ("bf16", 4)])
+@pytest.mark.parametrize("k", [3, 6, 11, 31])
+@pytest.mark.parametrize("dims", FUSED_DIMS)
+def test_fused_apply_matches_oracle_and_unfused(pc, dims, k, prec, S):
+    rp, ci, v = W.stencil7_csr(*dims)
+    lo, hi = W.stencil7_bounds(*dims)
+    n = len(rp) - 1
+    r = W.uniform(17, n, -1.0, 1.0)
+    z_ref = oracle.nc_apply_unscaled(rp, ci, v, r, lo, hi, k, 1.001)
+    outs = []
+    for fuse in (1, S):
+        with pc.pcheb_setup(pc.Operator.stencil7(*dims), k, lo, hi, 1.001, prec, fuse_steps=fuse) as h:
+            z = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+            pc.pcheb_apply(h, _t(r), z)
+            torch.cuda.synchronize()
+            outs.append(z.cpu().numpy())
+    assert rel_inf(outs[1], z_ref) <= APPLY_TOL[prec], (dims, k, prec, S, rel_inf(outs[1], z_ref))
+    # the fused pass does the unfused arithmetic in the same order
+    assert rel_inf(outs[1], outs[0]) <= {"f64": 1e-14, "f32": 1e-6, "bf16": 2e-2}[prec]
+
+
+@pytest.mark.parametrize("prec,S", [("f64", 3), ("f32", 4), ("bf16", 4)])
+def test_fused_solve_matches_oracle(pc, prec, S):
+    c = case("st7_cube")
+    k = 22
+    xstar, b = manufactured_rhs("st7_cube")
+    ref = oracle_solve("st7_cube", k, 1.001, True)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.001, prec, fuse_steps=S) as h:
+        x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st = pc.pcg_solve(h, _t(b), x, flexible=True)
+        x2 = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st2 = pc.pcg_solve(h, _t(b), x2, flexible=True, graph=False, time_kernels=True)
+    diff = np.linalg.norm(x.cpu().numpy() - ref.x_hat) / np.linalg.norm(ref.x_hat)
+    assert st["status"] == "OK" and abs(st["iters"] - ref.iters) <= 2 and diff <= 1e-6
+    assert st["relres_true"] <= TRUE_RES
+    assert st2["iters"] == st["iters"] and torch.equal(x, x2)
+    assert st2["step_launches"] == (k - 2) * st2["iters"]
