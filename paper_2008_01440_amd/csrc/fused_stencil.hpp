@@ -1,21 +1,28 @@
 // S consecutive middle steps of the Chebyshev recurrence on the matrix-free
 // 7-point operator in one pass over memory (temporal blocking).
 //
-// Step j needs y_{j-1} at a point and its 6 neighbours, y_{j-2} and s at the
+// Step j needs y_{j-1} at a point and its 6 neighbours and y_{j-2}, s at the
 // point, so S steps on a tile need y_{j-1} with a halo of S.  A block owns an
-// x-y tile of 64 x TY points and marches up a z range; for each of the S + 1
-// recurrence levels it keeps the last three planes of its (64 + 2S) x (TY + 2S)
-// region in LDS.  The levels run as a skewed pipeline: when input plane t
-// arrives, level l computes plane t - (l - 1) from level l-1's planes
-// z-1, z, z+1 and level l-2's plane z, on a region that shrinks by one point
-// per level, so level S+1 is exact on the 64 x TY interior.  One pass reads
-// y_{j-1}, y_{j-2} and s and writes y_{j+S-2}, y_{j+S-1}: 5 vectors moved for S
-// steps instead of 4 per step.  Halo points are recomputed by neighbouring
-// tiles; a z range is extended by S planes at each end.
+// x-y tile of 64 x TY points plus that halo (a region of RX x RY points) and
+// marches up a z range; the levels of the recurrence run as a skewed
+// pipeline: when input plane t arrives, level l computes plane t - (l - 1),
+// on a region that shrinks by one point per level, so level S+1 is exact on
+// the 64 x TY interior.  One pass reads y_{j-1}, y_{j-2} and s and writes
+// y_{j+S-2} and y_{j+S-1}: 5 vectors moved for S steps instead of 4 per step.
+// Halo points are recomputed by neighbouring tiles; a z range is extended by S
+// planes at each end.
 //
-// Level indices: level 1 is the input y_{j-1} (ring 0), level 0 the input
-// y_{j-2} (read from memory), level l >= 2 is y_{j+l-2} (ring l-1, levels
-// 2..S; level S+1 goes straight to memory).
+// Storage: every thread owns the same region points in every plane.  For
+// each level it keeps the last three planes of its points in registers (the
+// z neighbours), and the level's newest plane also goes to a double-buffered
+// LDS plane for the four in-plane neighbours.  Level l reads level l-1's plane
+// z, which level l-1 wrote in the previous step of the pipeline, so the levels
+// of one step never wait for each other: one barrier per step.  The global
+// loads of the next step are issued before the current step computes.
+//
+// Levels: level 1 is the input y_{j-1}, level 0 the input y_{j-2}, level
+// l >= 2 is y_{j+l-2}; levels 1..S have registers and LDS planes, level S+1
+// goes straight to memory.
 #pragma once
 
 #include "common.hpp"
@@ -26,8 +33,6 @@ template <class A, int S>
 struct FusedCoef {
   A a[S], b[S], c[S];  // step j + m uses a[m], b[m], c[m]
 };
-
-__device__ __forceinline__ int mod3(int z) { return ((z % 3) + 3) % 3; }
 
 template <int S, int TY, class T>
 __global__ __launch_bounds__(kBlock) void k_stencil7_fused(const T* __restrict__ ya, const T* __restrict__ yb,
@@ -41,7 +46,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil7_fused(const T* __restrict__
   constexpr int RX = TX + 2 * S;
   constexpr int RY = TY + 2 * S;
   constexpr int NP = RX * RY;
-  __shared__ acc ring[S][3][NP];
+  constexpr int P = (NP + kBlock - 1) / kBlock;  // region points per thread
+  __shared__ acc plane_buf[S][2][NP];
   if (guard && guard->done != kRunning) return;
   const int tid = threadIdx.x;
   const int64_t plane = int64_t(nx) * ny;
@@ -57,55 +63,103 @@ __global__ __launch_bounds__(kBlock) void k_stencil7_fused(const T* __restrict__
     const int z1 = z0 + zc < nz ? z0 + zc : nz;
     const int zs = z0 - S;
     const int nadv = (z1 - z0) + 2 * S;
+
+    // owned points: p = tid + kBlock m.  top[m] is the highest level whose
+    // region contains the point (0 outside the grid); inner[m] marks the tile
+    // interior; col[m] is the in-plane offset.
+    int col[P], top[P];
+    bool inner[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const int p = tid + kBlock * m;
+      const int ry = p / RX, rx = p - (p / RX) * RX;
+      const int gx = x0 + rx, gy = y0 + ry;
+      const bool dom = p < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      const int lx = rx + 1 < RX - rx ? rx + 1 : RX - rx;
+      const int ly = ry + 1 < RY - ry ? ry + 1 : RY - ry;
+      top[m] = dom ? (lx < ly ? lx : ly) : 0;
+      inner[m] = dom && rx >= S && rx < S + TX && ry >= S && ry < S + TY;
+      col[m] = dom ? gx + nx * gy : 0;
+    }
+    acc L[S][3][P];  // level l at [l-1]: [0] newest plane, [1] one below, [2] two below
+    acc sr[S][P];    // s at the planes of levels 2..S+1 ([0] = level 2's plane)
+    acc ybc[P];      // y_{j-2} at level 2's plane
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        L[l][0][m] = L[l][1][m] = L[l][2][m] = acc(0);
+        sr[l][m] = acc(0);
+      }
+    }
+    acc nya[P], ns[P], nyb[P];
+    auto fetch = [&](int za, int zb) {
+      const bool oka = za >= 0 && za < nz, okb = zb >= 0 && zb < nz;
+      const T* pa = ya + plane * (oka ? za : 0);
+      const T* ps = sv + plane * (okb ? zb : 0);
+      const T* pb = yb + plane * (okb ? zb : 0);
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        nya[m] = (oka && top[m] > 0) ? Store<T>::ld(pa, col[m]) : acc(0);
+        ns[m] = (okb && top[m] > 0) ? Store<T>::ld(ps, col[m]) : acc(0);
+        nyb[m] = (okb && top[m] > 0) ? Store<T>::ld(pb, col[m]) : acc(0);
+      }
+    };
+    fetch(zs, zs - 1);
     for (int adv = 0; adv < nadv; ++adv) {
-      // level 1: input plane zs + adv
-      {
-        const int z = zs + adv;
-        if (z >= 0 && z < nz) {
-          acc* dst = ring[0][mod3(z)];
-          for (int p = tid; p < NP; p += kBlock) {
-            const int ry = p / RX, rx = p - ry * RX;
-            const int gx = x0 + rx, gy = y0 + ry;
-            const bool dom = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            dst[p] = dom ? Store<T>::ld(ya, gx + int64_t(nx) * gy + plane * z) : acc(0);
-          }
-        }
-        __syncthreads();
+      acc cya[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        cya[m] = nya[m];
+#pragma unroll
+        for (int l = S - 1; l > 0; --l) sr[l][m] = sr[l - 1][m];
+        sr[0][m] = ns[m];
+        ybc[m] = nyb[m];
+      }
+      if (adv + 1 < nadv) fetch(zs + adv + 1, zs + adv);
+      // level 1: the input plane zs + adv
+      const int zin1 = zs + adv;
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        L[0][2][m] = L[0][1][m];
+        L[0][1][m] = L[0][0][m];
+        L[0][0][m] = cya[m];
+        if (tid + kBlock * m < NP) plane_buf[0][zin1 & 1][tid + kBlock * m] = cya[m];
       }
 #pragma unroll
       for (int l = 2; l <= S + 1; ++l) {
         const int z = zs + adv - (l - 1);
-        if (z >= 0 && z < nz) {
-          const acc a = cf.a[l - 2], b = cf.b[l - 2], c = cf.c[l - 2];
-          const acc* cen = ring[l - 2][mod3(z)];
-          const acc* up = ring[l - 2][mod3(z + 1)];
-          const acc* dn = ring[l - 2][mod3(z - 1)];
-          const bool has_up = z + 1 < nz, has_dn = z > 0;
-          const bool out_plane = z >= z0 && z < z1;
-          for (int p = tid; p < NP; p += kBlock) {
-            const int ry = p / RX, rx = p - ry * RX;
-            if (rx < l - 1 || rx > RX - l || ry < l - 1 || ry > RY - l) continue;
-            const int gx = x0 + rx, gy = y0 + ry;
-            const bool dom = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            acc v = acc(0);
-            const int64_t gi = gx + int64_t(nx) * gy + plane * z;
-            if (dom) {
-              const acc yc = cen[p];
-              acc nb = (cen[p - 1] + cen[p + 1]) + (cen[p - RX] + cen[p + RX]);
-              nb += (has_up ? up[p] : acc(0)) + (has_dn ? dn[p] : acc(0));
-              const acc yprev = (l == 2) ? Store<T>::ld(yb, gi) : ring[l >= 3 ? l - 3 : 0][mod3(z)][p];
-              v = a * yc + c * (Store<T>::ld(sv, gi) - (yc - nb * sixth));  // same order as EpiChebStep
-              v -= b * yprev;
-            }
-            if (l <= S) ring[l <= S ? l - 1 : 0][mod3(z)][p] = v;
-            if (out_plane && dom && rx >= S && rx < S + TX && ry >= S && ry < S + TY) {
-              if (l == S) Store<T>::st(out_b, gi, v);
-              if (l == S + 1) Store<T>::st(out_a, gi, v);
-            }
+        const bool zin = z >= 0 && z < nz;
+        const bool has_up = z + 1 < nz, has_dn = z > 0;
+        const bool out_plane = z >= z0 && z < z1;
+        const acc a = cf.a[l - 2], b = cf.b[l - 2], c = cf.c[l - 2];
+        const acc* nb_plane = plane_buf[l - 2][z & 1];  // level l-1, plane z (previous step)
+        const int li = l <= S ? l - 1 : 0;              // this level's register/LDS slot
+        const int lp = l >= 3 ? l - 3 : 0;              // level l-2 (y_{j-2} role) for l >= 3
+        T* out_z = (l == S ? out_b : out_a) + plane * (zin ? z : 0);
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+          const int p = tid + kBlock * m;
+          const bool valid = zin && l <= top[m];
+          acc v = acc(0);
+          if (valid) {
+            const acc yc = L[l - 2][1][m];
+            acc nb = (nb_plane[p - 1] + nb_plane[p + 1]) + (nb_plane[p - RX] + nb_plane[p + RX]);
+            nb += (has_up ? L[l - 2][0][m] : acc(0)) + (has_dn ? L[l - 2][2][m] : acc(0));
+            const acc yprev = (l == 2) ? ybc[m] : L[lp][2][m];
+            v = a * yc + c * (sr[l - 2][m] - (yc - nb * sixth));  // same order as EpiChebStep
+            v -= b * yprev;
+            if (l >= S && out_plane && inner[m]) Store<T>::st(out_z, col[m], v);
+          }
+          if (l <= S) {
+            L[li][2][m] = L[li][1][m];
+            L[li][1][m] = L[li][0][m];
+            L[li][0][m] = v;
+            if (p < NP) plane_buf[li][z & 1][p] = v;
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
   }
 }

@@ -419,9 +419,12 @@ static void launch_fused_any(const Handle& h, int S, const T* ya, const T* yb, T
   }
 }
 
-// Steps per pass: fusion applies to the 7-point operator with four iterate buffers.
+// Steps per pass: fusion applies to the 7-point operator with four iterate
+// buffers and x-y planes of fewer than 2^31 points (32-bit in-plane offsets).
 static int effective_fuse(const Handle& h) {
-  return (h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2 && h.nY >= 4) ? h.fuse : 1;
+  const bool ok = h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2 && h.nY >= 4 &&
+                  int64_t(h.op.nx) * h.op.ny < (int64_t(1) << 31);
+  return ok ? h.fuse : 1;
 }
 
 // Steps 1..k of Alg. 2 on the prepared input (s, y_0 = Y[0]); the last step
