@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG solves/s + P_k(A) HBM GB/s vs FP64 plain PCG; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_stencil7_256_traffic.md")
-KERNEL_SOURCES = ["operators.hpp", "epilogues.hpp", "common.hpp", "dispatch.hpp"]
+KERNEL_SOURCES = ["operators.hpp", "epilogues.hpp", "common.hpp", "dispatch.hpp", "fused_stencil.hpp", "pcheb.hip"]
 
 
 def log(*a):
@@ -45,7 +45,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec):
+def measured_traffic(prec, steps_per_pass):
     """HBM bytes per middle-step launch from the committed rocprofv3 counter summary,
     or None when it is missing or the kernel sources changed since it was taken."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -57,7 +57,7 @@ def measured_traffic(prec):
             vals[key.strip()] = v.strip()
     if vals.get("source_hash") != kernel_source_hash():
         return None
-    v = vals.get(f"traffic_bytes_per_launch_{prec}")
+    v = vals.get(f"traffic_bytes_per_launch_{prec}_s{steps_per_pass}")
     return float(v) if v else None
 
 
@@ -206,7 +206,7 @@ def main():
     alg_bytes = (5 if S > 1 else 4) * e * n
     avg_s = flag["step_avg_us"] * 1e-6 * S
     achieved = alg_bytes / avg_s / 1e9
-    traffic = measured_traffic(args.prec)
+    traffic = measured_traffic(args.prec, S)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": (f"k_stencil7_fused<S={S},{args.prec}> ({S} middle steps per launch)" if S > 1
