@@ -82,6 +82,14 @@ def main():
     ap.add_argument("--sweep-degrees", default="0,5,10,20,30,50,100", help="degrees of the sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="time the flagship only")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving scenario instead: Poisson arrivals of mixed 7-point / 27-point solves")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="50", help="arrival rates (req/s) to run; 'inf' submits all at once")
+    ap.add_argument("--serve-nrhs", type=int, default=4, help="concurrent solves per resident operator")
+    ap.add_argument("--serve-budget-gib", type=float, default=128.0)
+    ap.add_argument("--serve-k", type=int, default=30)
+    ap.add_argument("--serve-prec", default="f32", choices=["f64", "f32", "bf16"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -98,6 +106,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     pc.load_library()
+    if args.serve:
+        for rate in args.serve_rates.split(","):
+            run_serve(args, float(rate), torch, pc, W, dev)
+        return
     n1 = args.n
     n = n1 ** 3
 
@@ -260,6 +272,110 @@ def main():
         base = variants["fp64_plain_pcg"]["solves_per_s"]
         out["speedup_vs_fp64_plain_pcg"] = round(flag["solves_per_s"] / base, 3)
     print(json.dumps(out))
+
+
+def run_serve(args, rate, torch, pc, W, dev):
+    """Serving scenario: requests arrive as a Poisson process (seeded trace), each a
+    solve on a cubic grid with N uniform in [32, 160], half 7-point Laplacian (closed-form
+    bounds), half 27-point harmonic lognormal (bounds estimated by the server, counted in
+    latency); k = 30, float32 polynomial, float64 flexible PCG, tol 1e-8.  Operators with
+    equal (stencil, N) share resident data.  Latency runs from the scheduled arrival to
+    the host seeing the request done (solution in its device buffer).  A sample of the
+    served solutions is re-solved alone and compared bit for bit."""
+    tr = W.serving_trace(args.serve_requests, rate, seed=3)
+    nreq = len(tr["t"])
+    t0 = time.perf_counter()
+    ops, bounds = {}, {}
+    for kind, N, cs in sorted(set(zip(tr["kind"].tolist(), tr["N"].tolist(), tr["coeff_seed"].tolist()))):
+        if W.KINDS[kind] == "stencil7":
+            ops[(kind, N)] = pc.Operator.stencil7(N)
+            bounds[(kind, N)] = W.stencil7_bounds(N)
+        else:
+            kappa = torch.from_numpy(W.harmonic27_kappa(N, N, N, seed=cs)).to(dev)
+            ops[(kind, N)] = pc.Operator.stencil27h(kappa)
+            bounds[(kind, N)] = (0.0, 0.0)  # estimated by the server
+    torch.cuda.synchronize()
+    log(f"serve: {len(ops)} operators staged in {time.perf_counter() - t0:.1f}s; {nreq} requests at {rate} req/s")
+
+    check = {}  # request index -> (b, x) kept for the invariance check
+    want_check = set()
+    for kind in (0, 1):
+        idx = np.nonzero(tr["kind"] == kind)[0]
+        want_check.update(idx[:: max(1, len(idx) // 3)][:3].tolist())
+    srv = pc.Server(int(args.serve_budget_gib * (1 << 30)), args.serve_nrhs)
+    outstanding = {}  # id -> (request index, b, x)
+    lat, iters, status = [], [], {}
+    rejected = 0
+    start = time.perf_counter()
+    i = 0
+    while i < nreq or outstanding:
+        now = time.perf_counter() - start
+        while i < nreq and tr["t"][i] <= now:
+            kind, N = int(tr["kind"][i]), int(tr["N"][i])
+            n = N ** 3
+            b = torch.empty(n, dtype=torch.float64, device=dev)
+            pc.pcheb_fill_uniform(b, int(tr["rhs_seed"][i]), -1.0, 1.0)
+            x = torch.empty(n, dtype=torch.float64, device=dev)
+            lo, hi = bounds[(kind, N)]
+            try:
+                rid = srv.submit(ops[(kind, N)], b, x, args.serve_k, tol=1e-8, prec=args.serve_prec,
+                                 lambda_min=lo, lambda_max=hi, fuse_steps=2 if kind == 0 else 1)
+                outstanding[rid] = (i, b, x)
+            except pc.PchebError as e:
+                if e.name != "BUDGET":
+                    raise
+                rejected += 1
+            i += 1
+        for rid in list(outstanding):
+            st = srv.poll(rid)
+            if st is None:
+                continue
+            j, b, x = outstanding.pop(rid)
+            lat.append(time.perf_counter() - start - tr["t"][j])
+            iters.append(st["iters"])
+            status[st["status"]] = status.get(st["status"], 0) + 1
+            if j in want_check:
+                check[j] = (b, x, st)
+        if i < nreq and not outstanding:
+            time.sleep(max(0.0, min(0.002, tr["t"][i] - (time.perf_counter() - start))))
+        else:
+            time.sleep(0.0002)
+    wall = time.perf_counter() - start
+    sv = srv.stats()
+    srv.close()
+
+    # invariance: the sampled requests re-solved alone (same bounds) give the same bits
+    same = 0
+    for j, (b, x, st) in sorted(check.items()):
+        kind, N = int(tr["kind"][j]), int(tr["N"][j])
+        op = ops[(kind, N)]
+        lo, hi = bounds[(kind, N)]
+        if hi <= 0:
+            v0 = torch.empty(N ** 3, dtype=torch.float64, device=dev)
+            pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+            lo, hi = pc.pcheb_estimate_bounds(op, v0, 30)
+            hi *= 1.01
+        with pc.pcheb_setup(op, args.serve_k, lo, hi, 1.001, args.serve_prec,
+                            fuse_steps=2 if kind == 0 else 1) as h:
+            x1 = torch.empty_like(x)
+            st1 = pc.pcg_solve(h, b, x1, tol=1e-8, flexible=True)
+        same += int(torch.equal(x, x1) and st1["iters"] == st["iters"])
+    done = len(lat)
+    out = {
+        "mode": "serve", "requests": nreq, "rate_req_per_s": rate, "completed": done, "rejected": rejected,
+        "status": status, "wall_s": round(wall, 3), "throughput_solves_per_s": round(done / wall, 3),
+        "p50_latency_ms": round(1e3 * percentile(lat, 50), 3) if lat else None,
+        "p99_latency_ms": round(1e3 * percentile(lat, 99), 3) if lat else None,
+        "max_latency_ms": round(1e3 * max(lat), 3) if lat else None,
+        "mean_iters": round(float(np.mean(iters)), 2) if iters else None,
+        "k": args.serve_k, "prec": args.serve_prec, "max_nrhs": args.serve_nrhs,
+        "budget_gib": args.serve_budget_gib, "hbm_high_water_gib": round(sv["bytes_high_water"] / (1 << 30), 3),
+        "groups_created": sv["groups_created"], "groups_evicted": sv["groups_evicted"],
+        "launches": sv["launches"], "batch_hist": sv["batch_hist"],
+        "invariance": f"{same}/{len(check)} bitwise equal to solo solves",
+        "data": "synthetic", "n_gpus": 1,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def hbm_triad_ceiling(torch, dev, nbytes=1 << 30, reps=20):

@@ -204,6 +204,99 @@ size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int
 pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
                                    double* lambda_min, double* lambda_max, hipStream_t stream);
 
+/* Seeded uniform vector (workload generation, not part of the method):
+ * v[i] = lo + (hi - lo) * U_i for i < n, where U_i is element i of the
+ * counter-based SplitMix64 stream of `seed` (Steele, Lea & Flood, OOPSLA
+ * 2014): mix(seed + (i + 1) * 0x9E3779B97F4A7C15) with the SplitMix64
+ * finaliser, top 53 bits times 2^-53.  Bitwise equal to a sequential
+ * implementation of the same definition.  v: device float64[n], caller-owned.
+ * Stream-ordered, no host sync.  Errors: INVALID (n < 0, null v, lo > hi), HIP.
+ */
+pcheb_status pcheb_fill_uniform(double* v, int64_t n, uint64_t seed, double lo, double hi, hipStream_t stream);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A solve server with continuous batching.  Requests (an operator, a degree,
+ * a precision, a tolerance and a right-hand side) are admitted as long as
+ * the device memory they need fits the budget; requests with the same
+ * operator and parameters share one resident preconditioner (operator data,
+ * eigenvalue bounds, workspace for max_nrhs right-hand sides) and iterate
+ * together in multi-vector launches replayed from HIP graphs, each with its
+ * own scalars and stop test.  Requests join a running group between groups
+ * of iterations as slots free up, leave it when they converge, and groups of
+ * different operators run concurrently on their own streams.  A request's
+ * result does not depend on what else is being solved (same launches and
+ * reduction order per right-hand side).
+ *
+ * Every request iterates with the flexible (Polak-Ribiere) beta, so results
+ * equal those of pcg_solve with PCG_FLEXIBLE, x0 = 0, on the same parameters.
+ * Memory counted against the budget: pcheb_footprint_bytes(op, params,
+ * max_nrhs) plus 2 * max_nrhs * round_up(n, 64) doubles of right-hand-side
+ * and solution staging per resident group; a bound estimate borrows its
+ * Lanczos vectors for the duration of the group set-up only.
+ *
+ * One host thread owned by the server does all device work; the calls below
+ * may be made from any thread, except pserve_destroy, which must not race
+ * with the others.  A finished request's id is released once pserve_poll has
+ * reported it done or pserve_wait has returned; later calls with that id
+ * return NOT_FOUND.  Cancelling a request that is already finishing has no
+ * effect.
+ */
+typedef struct pserve_s* pserve_handle;
+
+typedef struct pserve_request {
+  pcheb_operator op;    /* device arrays borrowed until the request completes */
+  int32_t k;            /* degree */
+  int32_t prec;         /* pcheb_precision */
+  double lambda_min;    /* bounds of the scaled operator; lambda_max <= 0: estimate them */
+  double lambda_max;    /*   (30 Lanczos steps, lambda_max widened by 1.01; once per operator) */
+  double theta_scale;   /* modified parameter s >= 1 */
+  double tol;           /* relative residual tolerance */
+  int32_t maxit;
+  int32_t fuse_steps;
+  const double* b;      /* device float64[n], ready when submitted (the server reads it on its own
+                           stream, unordered with the caller's); read-only until the request completes */
+  double* x;            /* device float64[n]; receives the solution; complete when the request is
+                           reported done */
+  uint64_t op_key;      /* requests with equal op_key and equal operator fields share resident data */
+} pserve_request;
+
+typedef struct pserve_stats {
+  int64_t submitted, admitted, completed, rejected, cancelled;
+  int64_t queued, active;           /* now */
+  int64_t groups, groups_created, groups_evicted;
+  int64_t bytes_in_use, bytes_high_water, budget;
+  int64_t launches;                 /* iteration-group launches */
+  int64_t batch_hist[8];            /* launches with 1, 2, 3-4, 5-8, 9-16, 17-32, 33-64, >64 active solves */
+} pserve_stats;
+
+/* Create a server with a device-memory budget (bytes) and at most max_nrhs
+ * concurrent solves per resident operator (1..64), on the current device. */
+pcheb_status pserve_create(size_t hbm_budget, int32_t max_nrhs, pserve_handle* out);
+
+/* Queue a request; *id identifies it.  Returns BUDGET if the request alone
+ * needs more memory than the budget, INVALID for bad arguments. */
+pcheb_status pserve_submit(pserve_handle srv, const pserve_request* req, uint64_t* id);
+
+/* *done = 1 and stats filled once the request has finished (stats->seconds is
+ * the latency from submission to completion), else *done = 0.  NOT_FOUND for
+ * unknown ids. */
+pcheb_status pserve_poll(pserve_handle srv, uint64_t id, int32_t* done, pcg_stats* stats);
+
+/* Block until the request has finished; returns its solve status (OK,
+ * NOT_CONVERGED, BREAKDOWN; NOT_CONVERGED for a cancelled request), or the
+ * error that ended it (e.g. INVALID or NOT_SPD from the set-up of its
+ * operator, OOM). */
+pcheb_status pserve_wait(pserve_handle srv, uint64_t id, pcg_stats* stats);
+
+/* Drop a queued or running request; its slot is freed, others are unaffected. */
+pcheb_status pserve_cancel(pserve_handle srv, uint64_t id);
+
+pcheb_status pserve_get_stats(pserve_handle srv, pserve_stats* out);
+
+/* Stop the server (running requests are dropped) and free everything. */
+pcheb_status pserve_destroy(pserve_handle srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,12 +18,14 @@ from ._abi import (
     Handle,
     Operator,
     STATUS,
+    Server,
     library_path,
     load_library,
     pcg_solve,
     pcheb_apply,
     pcheb_destroy,
     pcheb_estimate_bounds,
+    pcheb_fill_uniform,
     pcheb_footprint_bytes,
     pcheb_last_error,
     pcheb_matvec,
@@ -40,12 +42,14 @@ __all__ = [
     "Handle",
     "Operator",
     "STATUS",
+    "Server",
     "library_path",
     "load_library",
     "pcg_solve",
     "pcheb_apply",
     "pcheb_destroy",
     "pcheb_estimate_bounds",
+    "pcheb_fill_uniform",
     "pcheb_footprint_bytes",
     "pcheb_last_error",
     "pcheb_matvec",

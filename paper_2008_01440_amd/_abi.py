@@ -83,6 +83,30 @@ class CStats(ctypes.Structure):
     ]
 
 
+class CServeRequest(ctypes.Structure):
+    _fields_ = [
+        ("op", COperator),
+        ("k", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("lambda_min", ctypes.c_double),
+        ("lambda_max", ctypes.c_double),
+        ("theta_scale", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int32),
+        ("fuse_steps", ctypes.c_int32),
+        ("b", ctypes.c_void_p),
+        ("x", ctypes.c_void_p),
+        ("op_key", ctypes.c_uint64),
+    ]
+
+
+class CServeStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "submitted", "admitted", "completed", "rejected", "cancelled", "queued", "active", "groups",
+        "groups_created", "groups_evicted", "bytes_in_use", "bytes_high_water", "budget", "launches")] + [
+        ("batch_hist", ctypes.c_int64 * 8)]
+
+
 _lib = None
 
 
@@ -111,8 +135,18 @@ def load_library():
     lib.pcheb_footprint_bytes.restype = ctypes.c_size_t
     lib.pcheb_estimate_bounds.argtypes = [ctypes.POINTER(COperator), vp, i32, ctypes.POINTER(f64),
                                           ctypes.POINTER(f64), vp]
+    lib.pcheb_fill_uniform.argtypes = [vp, i64, ctypes.c_uint64, f64, f64, vp]
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.pserve_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    lib.pserve_submit.argtypes = [vp, ctypes.POINTER(CServeRequest), u64p]
+    lib.pserve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(CStats)]
+    lib.pserve_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(CStats)]
+    lib.pserve_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.pserve_get_stats.argtypes = [vp, ctypes.POINTER(CServeStats)]
+    lib.pserve_destroy.argtypes = [vp]
     for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
-                 "pcheb_estimate_bounds"):
+                 "pcheb_estimate_bounds", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
+                 "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -138,16 +172,26 @@ def _stream(stream):
 
 
 def _dptr(t, dtype_name):
-    """Device pointer of a contiguous CUDA tensor with the expected dtype."""
+    """Device pointer of a CUDA tensor with the expected dtype: contiguous, or 2-D with
+    unit-stride rows (one vector per row, leading dimension = row stride)."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("expected a device (CUDA/HIP) tensor")
     if str(t.dtype) != f"torch.{dtype_name}":
         raise ValueError(f"expected dtype {dtype_name}, got {t.dtype}")
-    if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+    if not (t.is_contiguous() or (t.dim() == 2 and t.stride(1) == 1)):
+        raise ValueError("expected a contiguous tensor or rows with unit stride")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _rhs_layout(t, n):
+    """(nrhs, leading dimension) of a vector (n,) or a block of vectors (nrhs, >= n)."""
+    if t.dim() == 1:
+        return 1, n
+    if t.shape[1] != n:
+        raise ValueError(f"expected rows of length {n}, got {t.shape[1]}")
+    return t.shape[0], t.stride(0)
 
 
 class Operator:
@@ -219,14 +263,21 @@ def pcheb_setup(op: Operator, k: int, lambda_min: float, lambda_max: float, thet
     return Handle(out, op, p)
 
 
+def _same_layout(a, b, n):
+    la, lb = _rhs_layout(a, n), _rhs_layout(b, n)
+    if la != lb:
+        raise ValueError("input and output blocks must have the same shape and row stride")
+    return la
+
+
 def pcheb_apply(h: Handle, r, z, stream=None):
-    nrhs = 1 if r.dim() == 1 else r.shape[0]
-    _check(load_library().pcheb_apply(h.ptr, _dptr(r, "float64"), _dptr(z, "float64"), nrhs, h.n, _stream(stream)))
+    nrhs, ld = _same_layout(r, z, h.n)
+    _check(load_library().pcheb_apply(h.ptr, _dptr(r, "float64"), _dptr(z, "float64"), nrhs, ld, _stream(stream)))
 
 
 def pcheb_matvec(h: Handle, x, y, stream=None):
-    nrhs = 1 if x.dim() == 1 else x.shape[0]
-    _check(load_library().pcheb_matvec(h.ptr, _dptr(x, "float64"), _dptr(y, "float64"), nrhs, h.n,
+    nrhs, ld = _same_layout(x, y, h.n)
+    _check(load_library().pcheb_matvec(h.ptr, _dptr(x, "float64"), _dptr(y, "float64"), nrhs, ld,
                                         _stream(stream)))
 
 
@@ -239,8 +290,8 @@ def pcg_solve(h: Handle, b, x, tol: float = 1e-8, maxit: int = 100000, flexible:
              | (PCG_TIME_KERNELS if time_kernels else 0) | (0 if graph else PCG_NO_GRAPH)
              | (PCG_REFRESH if refresh else 0))
     st = CStats()
-    nrhs = 1 if b.dim() == 1 else b.shape[0]
-    status = load_library().pcg_solve(h.ptr, _dptr(b, "float64"), _dptr(x, "float64"), nrhs, h.n, tol, maxit,
+    nrhs, ld = _same_layout(b, x, h.n)
+    status = load_library().pcg_solve(h.ptr, _dptr(b, "float64"), _dptr(x, "float64"), nrhs, ld, tol, maxit,
                                       flags, ctypes.byref(st), _stream(stream))
     if check:
         _check(status, allowed=(0, 5))
@@ -266,3 +317,86 @@ def pcheb_estimate_bounds(op: Operator, v0, nsteps: int = 30, stream=None):
     _check(load_library().pcheb_estimate_bounds(ctypes.byref(op.c), _dptr(v0, "float64"), nsteps,
                                                 ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
     return lo.value, hi.value
+
+
+def pcheb_fill_uniform(v, seed: int, lo: float = 0.0, hi: float = 1.0, stream=None):
+    """v[i] = lo + (hi - lo) * U_i from the SplitMix64 stream of `seed` (float64 device vector)."""
+    _check(load_library().pcheb_fill_uniform(_dptr(v, "float64"), v.numel(), seed & 0xFFFFFFFFFFFFFFFF, lo, hi,
+                                             _stream(stream)))
+
+
+def _stats_dict(st: CStats, status) -> dict:
+    out = {name: getattr(st, name) for name, _ in CStats._fields_ if name != "pad0"}
+    out["status"] = STATUS.get(status, str(status))
+    return out
+
+
+class Server:
+    """A pserve_handle: continuous-batching solve server (see pserve_* in include/pcheb.h).
+
+    Requests borrow their operator tensors and the b / x vectors until they finish;
+    the server keeps references to them until then."""
+
+    def __init__(self, hbm_budget: int, max_nrhs: int = 16):
+        out = ctypes.c_void_p()
+        _check(load_library().pserve_create(int(hbm_budget), int(max_nrhs), ctypes.byref(out)))
+        self.ptr = out
+        self._keep = {}
+
+    def submit(self, op: Operator, b, x, k: int, tol: float = 1e-8, maxit: int = 100000, prec: str = "f64",
+               lambda_min: float = 0.0, lambda_max: float = 0.0, theta_scale: float = 1.001, fuse_steps: int = 1,
+               op_key: int = 0) -> int:
+        """Queue a solve; lambda_max <= 0 asks the server to estimate the bounds.  Returns the id."""
+        if b.shape != (op.n,) or x.shape != (op.n,):
+            raise ValueError(f"b and x must be vectors of length {op.n}")
+        req = CServeRequest(op=op.c, k=k, prec=PREC[prec] if isinstance(prec, str) else int(prec),
+                            lambda_min=lambda_min, lambda_max=lambda_max, theta_scale=theta_scale, tol=tol,
+                            maxit=maxit, fuse_steps=fuse_steps, b=_dptr(b, "float64"), x=_dptr(x, "float64"),
+                            op_key=op_key)
+        import torch
+        torch.cuda.current_stream().synchronize()  # b and x are used on the server's own streams
+        rid = ctypes.c_uint64()
+        _check(load_library().pserve_submit(self.ptr, ctypes.byref(req), ctypes.byref(rid)))
+        self._keep[rid.value] = (op, b, x)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while running, else the statistics dict (the id is then released)."""
+        done = ctypes.c_int32()
+        st = CStats()
+        _check(load_library().pserve_poll(self.ptr, rid, ctypes.byref(done), ctypes.byref(st)))
+        if not done.value:
+            return None
+        self._keep.pop(rid, None)
+        return _stats_dict(st, st.status)
+
+    def wait(self, rid: int, check: bool = False) -> dict:
+        """Block until the request finishes; the dict's 'status' is its final status."""
+        st = CStats()
+        status = load_library().pserve_wait(self.ptr, rid, ctypes.byref(st))
+        self._keep.pop(rid, None)
+        if check:
+            _check(status, allowed=(0, 5))
+        return _stats_dict(st, status)
+
+    def cancel(self, rid: int):
+        _check(load_library().pserve_cancel(self.ptr, rid))
+
+    def stats(self) -> dict:
+        st = CServeStats()
+        _check(load_library().pserve_get_stats(self.ptr, ctypes.byref(st)))
+        out = {name: getattr(st, name) for name, _ in CServeStats._fields_ if name != "batch_hist"}
+        out["batch_hist"] = list(st.batch_hist)
+        return out
+
+    def close(self):
+        if self.ptr:
+            _check(load_library().pserve_destroy(self.ptr))
+            self.ptr = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -140,27 +140,36 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
 // result is reproducible for a given grid) and calls fin(total).  The kernel
 // boundary makes the slots visible, so no block needs a device-scope fence
 // (on a multi-XCD part such a fence writes back and invalidates the whole
-// L2 of the die) and no atomic counter is contended.
+// L2 of the die) and no atomic counter is contended.  Every right-hand side
+// (solve slot) has its own kMaxGrid partial slots.
+__device__ __forceinline__ size_t partial_index(int slot, uint32_t block) {
+  return (size_t(slot) * kMaxGrid + block) * kMaxReduce;
+}
+
 template <int NV>
-__device__ __forceinline__ void block_partial(double (&v)[NV], ReduceBuf rb) {
+__device__ __forceinline__ void block_partial(double (&v)[NV], ReduceBuf rb, int slot) {
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   block_sum<NV>(v, tid);
   if (tid == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) rb.partials[size_t(blockIdx.x) * kMaxReduce + i] = v[i];
+    for (int i = 0; i < NV; ++i) rb.partials[partial_index(slot, blockIdx.x) + i] = v[i];
   }
 }
 
+// One block per solve slot (slot = slot0 + blockIdx.x); fin.bind(slot) points
+// the functor at that slot's state before fin(total).
 template <int NV, class Fin>
-__global__ __launch_bounds__(kBlock) void k_finalize(Fin fin, ReduceBuf rb, uint32_t nblocks,
-                                                     const DevState* guard) {
-  if (guard && guard->done != kRunning) return;
+__global__ __launch_bounds__(kBlock) void k_finalize(Fin fin, ReduceBuf rb, uint32_t nblocks, const DevState* guard,
+                                                     int slot0) {
+  const int slot = slot0 + int(blockIdx.x);
+  if (guard && guard[slot].done != kRunning) return;
+  fin.bind(slot);
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += rb.partials[size_t(b) * kMaxReduce + i];
+    for (int i = 0; i < NV; ++i) acc[i] += rb.partials[partial_index(slot, b) + i];
   }
   block_sum<NV>(acc, threadIdx.x);
   if (threadIdx.x == 0) fin(acc);

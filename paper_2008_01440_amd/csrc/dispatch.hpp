@@ -26,8 +26,10 @@ inline StencilGrid stencil_grid(const pcheb_operator& op) {
 }
 
 // Tv: value type of CSR/SELL arrays (float64 for A_hat; storage type for D^-1 A_hat).
+// The launch covers solve slots slot0 .. slot0 + nslots - 1 (grid dimension y).
 template <bool SCALED, class Tv, class In, class Epi>
-void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Epi epi, hipStream_t s) {
+void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Epi epi, int slot0, int nslots,
+               hipStream_t s) {
   using acc = typename Epi::acc;
   const pcheb_operator& op = h.op;
   uint32_t grid = 0;
@@ -35,8 +37,8 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     case PCHEB_OP_STENCIL7: {
       const StencilGrid g = stencil_grid(op);
       grid = g.grid;
-      k_stencil7<SCALED, kZChunk, In, Epi><<<grid, dim3(64, 4), 0, s>>>(in, epi, op.nx, op.ny, op.nz, g.tiles_x,
-                                                                      g.tiles_y, g.ntiles, h.rb());
+      k_stencil7<SCALED, kZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
+          in, epi, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_STENCIL27H: {
@@ -48,8 +50,8 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       } else {
         kappa = reinterpret_cast<const acc*>(h.kappa_lo);
       }
-      k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<grid, dim3(64, 4), 0, s>>>(
-          in, epi, kappa, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb());
+      k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
+          in, epi, kappa, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_CSR: {
@@ -58,8 +60,8 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       grid = round_grid(tiles);
 #define PCHEB_CSR_CASE(L)                                                                              \
   case L:                                                                                              \
-    k_csr<L, Tv, In, Epi><<<grid, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n, uint32_t(tiles), \
-                                                 h.rb());                                              \
+    k_csr<L, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n,   \
+                                                               uint32_t(tiles), h.rb(), slot0);                \
     break;
       switch (h.lanes) {
         PCHEB_CSR_CASE(4)
@@ -75,28 +77,30 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     case PCHEB_OP_SELL: {
       const uint64_t tiles = uint64_t((h.nchunks + 3) / 4);
       grid = round_grid(tiles);
-      k_sell<Tv, In, Epi><<<grid, kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val, h.sell_perm, in, epi,
-                                                  h.n, uint32_t(tiles), h.rb());
+      k_sell<Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val,
+                                                                h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(),
+                                                                slot0);
       break;
     }
     default:
       fail(PCHEB_INVALID, "unknown operator kind");
   }
   if constexpr (Epi::reduce) {
-    k_finalize<Epi::NV, EpiFin<Epi>><<<1, kBlock, 0, s>>>(EpiFin<Epi>{epi}, h.rb(), grid, epi.guard);
+    k_finalize<Epi::NV, EpiFin<Epi>><<<nslots, kBlock, 0, s>>>(EpiFin<Epi>{epi}, h.rb(), grid, epi.guard, slot0);
   }
 }
 
 // A_hat applied to a float64 input functor (the outer iteration and residuals).
 template <class In, class Epi>
-void launch_ahat(const Handle& h, In in, Epi epi, hipStream_t s) {
-  launch_op<false, double>(h, h.op.values, h.sell_aval, in, epi, s);
+void launch_ahat(const Handle& h, In in, Epi epi, int slot0, int nslots, hipStream_t s) {
+  launch_op<false, double>(h, h.op.values, h.sell_aval, in, epi, slot0, nslots, s);
 }
 
 // D^-1 A_hat applied to an input in the storage precision T.
 template <class T, class In, class Epi>
-void launch_bop(const Handle& h, In in, Epi epi, hipStream_t s) {
-  launch_op<true, T>(h, reinterpret_cast<const T*>(h.csr_bval), reinterpret_cast<const T*>(h.sell_bval), in, epi, s);
+void launch_bop(const Handle& h, In in, Epi epi, int slot0, int nslots, hipStream_t s) {
+  launch_op<true, T>(h, reinterpret_cast<const T*>(h.csr_bval), reinterpret_cast<const T*>(h.sell_bval), in, epi,
+                     slot0, nslots, s);
 }
 
 }  // namespace pcheb

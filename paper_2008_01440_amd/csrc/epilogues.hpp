@@ -34,6 +34,14 @@ struct EpiChebStep {
   acc a, b, c;
   DevState* st;
   const DevState* guard;
+  int64_t ld;
+  __device__ __forceinline__ void bind(int slot) {
+    const int64_t o = slot * ld;
+    if (!FIRST) yprev += o;
+    s += o;
+    out += o;
+    if (guard) guard += slot;
+  }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, double (&)[NV]) const {
     acc v = a * y + c * (Store<T>::ld(s, i) - by);
@@ -66,6 +74,17 @@ struct EpiChebLast {
   const DevState* guard;
   int init;
   int flexible;
+  int64_t ld;
+  __device__ __forceinline__ void bind(int slot) {
+    const int64_t o = slot * ld;
+    if (!FIRST) yprev += o;
+    s += o;
+    z += o;
+    r += o;
+    if (q) q += o;
+    if (st) st += slot;
+    if (guard) guard += slot;
+  }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, double (&part)[NV]) const {
     acc v = a * y + c * (Store<T>::ld(s, i) - by);
@@ -106,6 +125,13 @@ struct EpiDirection {
   double* q;
   DevState* st;
   const DevState* guard;
+  int64_t ld;
+  __device__ __forceinline__ void bind(int slot) {
+    p_new += slot * ld;
+    q += slot * ld;
+    st += slot;
+    if (guard) guard += slot;
+  }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, double p, double ap, double (&part)[NV]) const {
     p_new[i] = p;
@@ -131,6 +157,8 @@ struct EpiStore {
   T* y;
   DevState* st;
   const DevState* guard;
+  int64_t ld;
+  __device__ __forceinline__ void bind(int slot) { y += slot * ld; }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, acc, acc m, double (&)[NV]) const { Store<T>::st(y, i, m); }
   __device__ void fin(double (&)[NV]) const {}
@@ -145,6 +173,8 @@ struct EpiScaledStore {
   const double* isd;
   DevState* st;
   const DevState* guard;
+  int64_t ld;
+  __device__ __forceinline__ void bind(int slot) { w += slot * ld; }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, double, double m, double (&)[NV]) const { w[i] = m * isd[i]; }
   __device__ void fin(double (&)[NV]) const {}
@@ -164,6 +194,14 @@ struct EpiResidual {
   DevState* st;
   const DevState* guard;
   int mode;
+  int64_t ldb;  // stride of the caller's right-hand sides
+  int64_t ldr;  // stride of the workspace residuals
+  __device__ __forceinline__ void bind(int slot) {
+    b += slot * ldb;
+    if (r) r += slot * ldr;
+    st += slot;
+    if (guard) guard += slot;
+  }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, double, double ax, double (&part)[NV]) const {
     const double bi = b[i];

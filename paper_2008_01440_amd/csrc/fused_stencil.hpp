@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil7_fused(const T* __restrict__
                                                            T* __restrict__ out_b,
                                                            FusedCoef<typename Store<T>::acc, S> cf, int nx, int ny,
                                                            int nz, int zc, uint32_t tiles_x, uint32_t tiles_y,
-                                                           uint32_t ntiles, const DevState* guard) {
+                                                           uint32_t ntiles, const DevState* guard, int64_t ld,
+                                                           int slot0) {
   using acc = typename Store<T>::acc;
   constexpr int TX = 64;
   constexpr int RX = TX + 2 * S;
@@ -48,7 +49,13 @@ __global__ __launch_bounds__(kBlock) void k_stencil7_fused(const T* __restrict__
   constexpr int NP = RX * RY;
   constexpr int P = (NP + kBlock - 1) / kBlock;  // region points per thread
   __shared__ acc plane_buf[S][2][NP];
-  if (guard && guard->done != kRunning) return;
+  const int slot = slot0 + int(blockIdx.y);  // solve slot: vectors offset by slot * ld
+  if (guard && guard[slot].done != kRunning) return;
+  ya += slot * ld;
+  yb += slot * ld;
+  sv += slot * ld;
+  out_a += slot * ld;
+  out_b += slot * ld;
   const int tid = threadIdx.x;
   const int64_t plane = int64_t(nx) * ny;
   const acc sixth = acc(1.0 / 6.0);

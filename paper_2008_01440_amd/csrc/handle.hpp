@@ -55,28 +55,34 @@ struct Handle {
   int32_t* sell_perm = nullptr; // null when sigma == 1
   void* kappa_lo = nullptr;     // STENCIL27H: float32 copy of the coefficients
 
-  // workspace for one right-hand side
-  void* s = nullptr;          // D^-1 r (storage precision)
-  void* Y[4] = {nullptr, nullptr, nullptr, nullptr};  // recurrence iterates (storage precision)
+  // solve workspace for `cap` right-hand sides (slots); vectors of slot j start
+  // at j * ldw elements.  Allocated on demand, separately from the operator data.
+  int cap = 0;
+  int64_t ldw = 0;
   int nY = 3;                 // iterate buffers in use (4 when steps are fused)
   int fuse = 1;               // recurrence steps per pass (7-point stencil only)
+  void* s = nullptr;          // D^-1 r (storage precision)
+  void* Y[4] = {nullptr, nullptr, nullptr, nullptr};  // recurrence iterates (storage precision)
   double* r = nullptr;
   double* p[2] = {nullptr, nullptr};
   double* q = nullptr;
   double* z = nullptr;
-  DevState* st = nullptr;     // device scalars of the current solve
-  DevState* st_host = nullptr;  // pinned host mirror (two slots)
-  double* partials = nullptr;
+  DevState* st = nullptr;       // device scalars, one per slot
+  DevState* st_host = nullptr;  // pinned host mirror: two groups of cap states
+  double* partials = nullptr;   // cap * kMaxGrid * kMaxReduce
 
   // graph cache for the PCG iteration pair (captured on a private stream,
   // launched on the caller's; the legacy null stream cannot be captured)
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   const double* graph_x = nullptr;
+  int64_t graph_ldx = 0;
+  int graph_slots = 0;
   uint32_t graph_flags = 0;
 
   std::vector<hipEvent_t> events;
-  std::vector<DeviceBuffer> owned;
+  std::vector<DeviceBuffer> owned;     // operator data
+  std::vector<DeviceBuffer> owned_ws;  // solve workspace
 
   ReduceBuf rb() const { return ReduceBuf{partials}; }
 };
@@ -84,6 +90,12 @@ struct Handle {
 void* dev_alloc(Handle& h, size_t bytes);
 void setup_operator(Handle& h, hipStream_t s);
 void release(Handle& h);
+
+// A contiguous range of solve slots covered by one launch.
+struct Slots {
+  int first;
+  int count;
+};
 
 inline uint32_t round_grid(uint64_t tiles) {
   uint64_t g = tiles < uint64_t(kMaxGrid) ? tiles : uint64_t(kMaxGrid);

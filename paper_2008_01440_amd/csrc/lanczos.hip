@@ -106,7 +106,7 @@ static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double
   std::vector<double> alpha, beta;
   for (int j = 0; j < m; ++j) {
     const double* vj = V + int64_t(j) * n;
-    launch_ahat(h, InScaled{vj, isd}, EpiScaledStore{w, isd, nullptr, nullptr}, s);
+    launch_ahat(h, InScaled{vj, isd, n}, EpiScaledStore{w, isd, nullptr, nullptr, n}, 0, 1, s);
     PCHEB_HIP_CHECK(hipGetLastError());
     dots(vj, 1, w, n, partial, host, out, s);
     alpha.push_back(out[0]);

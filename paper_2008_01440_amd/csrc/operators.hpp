@@ -7,11 +7,19 @@
 // input vector is read through an input functor, so a kernel can form its
 // input on the fly (p = z + beta p_old) instead of reading a stored vector.
 //
+// Every launch covers one or more solve slots (right-hand sides): slot =
+// slot0 + blockIdx.y.  bind(slot) points a functor at that slot's vectors
+// (offset slot * ld elements) and state; operator data is shared by all slots.
+// The tiling of a slot does not depend on how many slots share the launch, so
+// results are the same alone and batched.
+//
 // Interfaces
-//   In:  using acc; __device__ void prepare(); __device__ acc ld(int64_t i) const;
+//   In:  using acc; int64_t stride; __device__ void bind(int slot); __device__ void prepare();
+//        __device__ acc ld(int64_t i) const;
 //   Epi: using acc; static constexpr int NV; static constexpr bool reduce;
 //        DevState* st (may be null; written by fin); const DevState* guard (may be
-//        null; the kernel does nothing once guard->done is set); __device__ void prepare();
+//        null; the kernel does nothing once guard->done is set); __device__ void bind(int slot);
+//        __device__ void prepare();
 //        __device__ void operator()(int64_t i, acc yi, acc mi, double (&part)[NV]) const;
 //        __device__ void fin(double (&total)[NV]) const;   // thread 0 of the finalize kernel
 //
@@ -29,16 +37,28 @@ __device__ __forceinline__ bool solve_finished(const Epi& epi) {
 }
 
 template <class Epi>
-__device__ __forceinline__ void finish_reduction(const Epi&, double (&part)[Epi::NV], ReduceBuf rb) {
-  if constexpr (Epi::reduce) block_partial<Epi::NV>(part, rb);
+__device__ __forceinline__ void finish_reduction(const Epi&, double (&part)[Epi::NV], ReduceBuf rb, int slot) {
+  if constexpr (Epi::reduce) block_partial<Epi::NV>(part, rb, slot);
 }
 
 // Calls epi.fin(total) from the finalize kernel.
 template <class Epi>
 struct EpiFin {
   Epi epi;
+  __device__ __forceinline__ void bind(int slot) { epi.bind(slot); }
   __device__ __forceinline__ void operator()(double (&t)[Epi::NV]) const { epi.fin(t); }
 };
+
+// Point the functors at this block's slot; true if the slot's solve has finished.
+template <class In, class Epi>
+__device__ __forceinline__ bool bind_slot(In& in, Epi& epi, int slot) {
+  in.bind(slot);
+  epi.bind(slot);
+  if (solve_finished(epi)) return true;
+  in.prepare();
+  epi.prepare();
+  return false;
+}
 
 // ------------------------------------------------------------------ 7-point stencil
 //
@@ -49,11 +69,10 @@ struct EpiFin {
 template <bool SCALED, int ZC, class In, class Epi>
 __global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int ny, int nz,
                                                      uint32_t tiles_x, uint32_t tiles_y, uint32_t ntiles,
-                                                     ReduceBuf rb) {
+                                                     ReduceBuf rb, int slot0) {
   using acc = typename Epi::acc;
-  if (solve_finished(epi)) return;
-  in.prepare();
-  epi.prepare();
+  const int slot = slot0 + int(blockIdx.y);
+  if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
@@ -85,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int
       centre = above;
     }
   }
-  finish_reduction(epi, part, rb);
+  finish_reduction(epi, part, rb, slot);
 }
 
 // ------------------------------------------------------------------ 27-point harmonic stencil
@@ -97,11 +116,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int
 template <bool SCALED, int ZC, class KT, class In, class Epi>
 __global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT* __restrict__ kappa, int nx,
                                                        int ny, int nz, uint32_t tiles_x, uint32_t tiles_y,
-                                                       uint32_t ntiles, ReduceBuf rb) {
+                                                       uint32_t ntiles, ReduceBuf rb, int slot0) {
   using acc = typename Epi::acc;
-  if (solve_finished(epi)) return;
-  in.prepare();
-  epi.prepare();
+  const int slot = slot0 + int(blockIdx.y);
+  if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
@@ -172,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT*
       }
     }
   }
-  finish_reduction(epi, part, rb);
+  finish_reduction(epi, part, rb, slot);
 }
 
 // ------------------------------------------------------------------ CSR
@@ -183,11 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT*
 template <int LANES, class Tv, class In, class Epi>
 __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                 const Tv* __restrict__ val, In in, Epi epi, int64_t n,
-                                                uint32_t ntiles, ReduceBuf rb) {
+                                                uint32_t ntiles, ReduceBuf rb, int slot0) {
   using acc = typename Epi::acc;
-  if (solve_finished(epi)) return;
-  in.prepare();
-  epi.prepare();
+  const int slot = slot0 + int(blockIdx.y);
+  if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
@@ -205,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
     for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
     if (row < n && g == 0) epi(row, in.ld(row), sum, part);
   }
-  finish_reduction(epi, part, rb);
+  finish_reduction(epi, part, rb, slot);
 }
 
 // ------------------------------------------------------------------ SELL-C-sigma, C = 64
@@ -219,11 +236,10 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
                                                  const int32_t* __restrict__ chunk_len,
                                                  const int32_t* __restrict__ col, const Tv* __restrict__ val,
                                                  const int32_t* __restrict__ perm, In in, Epi epi, int64_t n,
-                                                 uint32_t ntiles, ReduceBuf rb) {
+                                                 uint32_t ntiles, ReduceBuf rb, int slot0) {
   using acc = typename Epi::acc;
-  if (solve_finished(epi)) return;
-  in.prepare();
-  epi.prepare();
+  const int slot = slot0 + int(blockIdx.y);
+  if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
@@ -245,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
       epi(row, in.ld(row), sum, part);
     }
   }
-  finish_reduction(epi, part, rb);
+  finish_reduction(epi, part, rb, slot);
 }
 
 // ------------------------------------------------------------------ input functors
@@ -254,6 +270,8 @@ template <class T>
 struct InVec {
   using acc = typename Store<T>::acc;
   const T* p;
+  int64_t stride;
+  __device__ __forceinline__ void bind(int slot) { p += slot * stride; }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ acc ld(int64_t i) const { return Store<T>::ld(p, i); }
 };
@@ -265,6 +283,12 @@ struct InDirection {
   const double* p_old;
   const DevState* st;
   double beta;
+  int64_t stride;
+  __device__ __forceinline__ void bind(int slot) {
+    z += slot * stride;
+    p_old += slot * stride;
+    st += slot;
+  }
   __device__ __forceinline__ void prepare() { beta = st->beta; }
   __device__ __forceinline__ double ld(int64_t i) const { return z[i] + beta * p_old[i]; }
 };
@@ -273,7 +297,9 @@ struct InDirection {
 struct InScaled {
   using acc = double;
   const double* v;
-  const double* isd;  // 1 / sqrt(diag)
+  const double* isd;  // 1 / sqrt(diag), shared by all slots
+  int64_t stride;
+  __device__ __forceinline__ void bind(int slot) { v += slot * stride; }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ double ld(int64_t i) const { return v[i] * isd[i]; }
 };

@@ -1,6 +1,7 @@
 // pcheb: set-up, preconditioner application, operator product and the PCG
 // driver of the Newton-Chebyshev preconditioned CG (arXiv:2008.01440) on
-// gfx950.  The C ABI is declared in include/pcheb.h.
+// gfx950.  The C ABI is declared in include/pcheb.h; the solver internals the
+// serving engine also uses are declared in solver.hpp.
 
 #include <hip/hip_runtime.h>
 
@@ -15,6 +16,7 @@
 #include "dispatch.hpp"
 #include "fused_stencil.hpp"
 #include "handle.hpp"
+#include "solver.hpp"
 
 namespace pcheb {
 
@@ -24,6 +26,8 @@ static thread_local std::string g_last_error;
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
 void fail(pcheb_status st, const std::string& msg) { throw Error{st, msg}; }
 
 void check_hip(hipError_t e, const char* what) {
@@ -32,7 +36,7 @@ void check_hip(hipError_t e, const char* what) {
   fail(st, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void* dev_alloc(Handle& h, size_t bytes) {
+static void* alloc_into(std::vector<DeviceBuffer>& list, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
   const hipError_t e = hipMalloc(&p, bytes);
@@ -41,24 +45,40 @@ void* dev_alloc(Handle& h, size_t bytes) {
     fail(e == hipErrorOutOfMemory ? PCHEB_OOM : PCHEB_HIP,
          "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
   }
-  h.owned.push_back(DeviceBuffer{p, bytes});
+  list.push_back(DeviceBuffer{p, bytes});
   return p;
 }
 
-void release(Handle& h) {
+void* dev_alloc(Handle& h, size_t bytes) { return alloc_into(h.owned, bytes); }
+
+static void drop_graph(Handle& h) {
   if (h.graph_exec) (void)hipGraphExecDestroy(h.graph_exec);
   h.graph_exec = nullptr;
+  h.graph_x = nullptr;
+}
+
+static void release_workspace(Handle& h) {
+  drop_graph(h);
+  if (h.st_host) (void)hipHostFree(h.st_host);
+  h.st_host = nullptr;
+  for (auto& b : h.owned_ws) (void)hipFree(b.ptr);
+  h.owned_ws.clear();
+  h.cap = 0;
+}
+
+void release(Handle& h) {
+  release_workspace(h);
   if (h.capture_stream) (void)hipStreamDestroy(h.capture_stream);
   h.capture_stream = nullptr;
   for (hipEvent_t e : h.events) (void)hipEventDestroy(e);
   h.events.clear();
-  if (h.st_host) (void)hipHostFree(h.st_host);
-  h.st_host = nullptr;
   for (auto& b : h.owned) (void)hipFree(b.ptr);
   h.owned.clear();
 }
 
 static size_t storage_bytes(int prec) { return prec == PCHEB_F64 ? 8 : (prec == PCHEB_F32 ? 4 : 2); }
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // ================================================================ elementwise kernels
 
@@ -169,6 +189,8 @@ __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
 
 // Elementwise kernels walk the vectors in pairs of elements (16-byte float64
 // accesses; every vector is 16-byte aligned), with a scalar tail for odd n.
+// blockIdx.y selects the solve slot (slot0 + blockIdx.y); workspace vectors
+// of slot j start at j * ldw, caller vectors at j * ld of the caller.
 #define PAIR_STRIDE(i, n)                                                                  \
   for (int64_t i = 2 * (int64_t(blockIdx.x) * blockDim.x + threadIdx.x); i < (n);           \
        i += 2 * int64_t(gridDim.x) * blockDim.x)
@@ -181,6 +203,7 @@ __device__ __forceinline__ double2 invd2(InvDiag d, int64_t i) {
 
 struct FinStart {
   DevState* st;
+  __device__ void bind(int slot) { st += slot; }
   __device__ void operator()(double (&t)[2]) const {
     st->bb = t[0];
     st->rr = t[0];
@@ -193,6 +216,7 @@ struct FinStart {
 struct FinBeta {
   DevState* st;
   int init, flexible;
+  __device__ void bind(int slot) { st += slot; }
   __device__ void operator()(double (&t)[2]) const {
     EpiChebLast<double, true, true>::finish_beta(st, t[0], t[1], init, flexible);
   }
@@ -203,6 +227,7 @@ struct FinBeta {
 template <int MODE>
 struct FinUpdate {
   DevState* st;
+  __device__ void bind(int slot) { st += slot; }
   __device__ void operator()(double (&t)[3]) const {
     st->rr = t[0];
     st->iter += 1;
@@ -220,8 +245,13 @@ struct FinUpdate {
 };
 
 // x0 = 0: x = 0, r = b, p_old = 0 and the norms of b.
-__global__ void k_start_zero(const double* b, double* x, double* r, double* p_old, InvDiag invd, int64_t n,
-                             ReduceBuf rb) {
+__global__ void k_start_zero(const double* b, int64_t ldb, double* x, int64_t ldx, double* r, double* p_old,
+                             int64_t ldw, InvDiag invd, int64_t n, ReduceBuf rb, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  b += slot * ldb;
+  x += slot * ldx;
+  r += slot * ldw;
+  p_old += slot * ldw;
   double part[2] = {0.0, 0.0};
   PAIR_STRIDE(i, n) {
     if (i + 1 < n) {
@@ -240,14 +270,24 @@ __global__ void k_start_zero(const double* b, double* x, double* r, double* p_ol
       part[1] += bi * bi;
     }
   }
-  block_partial<2>(part, rb);
+  block_partial<2>(part, rb, slot);
+}
+
+// p_old = 0 for the slots of a warm start.
+__global__ void k_zero_slots(double* p, int64_t ldw, int64_t n, int slot0) {
+  p += (slot0 + int64_t(blockIdx.y)) * ldw;
+  GRID_STRIDE(i, n) p[i] = 0.0;
 }
 
 // Preconditioner input: s = D^-1 r and y_0 = s / theta' in the storage precision.
 template <class T>
-__global__ void k_prep(const double* r, T* s, T* y0, InvDiag invd, double inv_theta, int64_t n,
-                       const DevState* guard) {
-  if (guard && guard->done != kRunning) return;
+__global__ void k_prep(const double* r, int64_t ldr, T* s, T* y0, int64_t ldw, InvDiag invd, double inv_theta,
+                       int64_t n, const DevState* guard, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  r += slot * ldr;
+  s += slot * ldw;
+  y0 += slot * ldw;
   using acc = typename Store<T>::acc;
   PAIR_STRIDE(i, n) {
     if (i + 1 < n) {
@@ -265,9 +305,14 @@ __global__ void k_prep(const double* r, T* s, T* y0, InvDiag invd, double inv_th
 
 // Degree 0: z = D^-1 r / theta' (the diagonal preconditioner), optionally with
 // the dot products (r, z), (z, q) whose finalize forms beta.
-__global__ void k_jacobi(const double* r, double* z, const double* q, InvDiag invd, double inv_theta, int64_t n,
-                         const DevState* guard, ReduceBuf rb, int dots, int flexible) {
-  if (guard && guard->done != kRunning) return;
+__global__ void k_jacobi(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q, InvDiag invd,
+                         double inv_theta, int64_t n, const DevState* guard, ReduceBuf rb, int dots, int flexible,
+                         int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  r += slot * ldr;
+  z += slot * ldz;
+  if (q) q += slot * ldz;
   double part[2] = {0.0, 0.0};
   PAIR_STRIDE(i, n) {
     if (i + 1 < n) {
@@ -287,7 +332,7 @@ __global__ void k_jacobi(const double* r, double* z, const double* q, InvDiag in
       if (flexible) part[1] += zi * q[i];
     }
   }
-  if (dots) block_partial<2>(part, rb);
+  if (dots) block_partial<2>(part, rb, slot);
 }
 
 // Iteration update x += alpha p, r -= alpha q with ||r||^2 (D^-1 weighted), and
@@ -297,9 +342,22 @@ __global__ void k_jacobi(const double* r, double* z, const double* q, InvDiag in
 //   MODE 2:          nothing else (the residual is refreshed before the next step).
 // The stop test runs in the finalize kernel (FinUpdate).
 template <class T, int MODE>
-__global__ void k_update(double* x, double* r, const double* p, const double* q, InvDiag invd, T* s, T* y0,
-                         double* z, double inv_theta, int64_t n, const DevState* st, ReduceBuf rb) {
+__global__ void k_update(double* x, int64_t ldx, double* r, const double* p, const double* q, int64_t ldw,
+                         InvDiag invd, T* s, T* y0, double* z, double inv_theta, int64_t n, const DevState* st,
+                         ReduceBuf rb, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  st += slot;
   if (st->done != kRunning) return;
+  const int64_t o = slot * ldw;
+  x += slot * ldx;
+  r += o;
+  p += o;
+  q += o;
+  if (MODE == 0) {
+    s += o;
+    y0 += o;
+  }
+  if (MODE == 1) z += o;
   using acc = typename Store<T>::acc;
   const double alpha = st->alpha;
   const int flexible = st->flexible;
@@ -340,7 +398,7 @@ __global__ void k_update(double* x, double* r, const double* p, const double* q,
       }
     }
   }
-  block_partial<3>(part, rb);
+  block_partial<3>(part, rb, slot);
 }
 
 // ================================================================ preconditioner
@@ -365,7 +423,6 @@ static InvDiag invdiag(const Handle& h) { return InvDiag{h.invd, h.invd ? 0.0 : 
 
 // Optional timing of the middle steps (2 .. k-1) of each application.
 struct StepTimer {
-  std::vector<hipEvent_t>* pool = nullptr;
   size_t used = 0;
   hipEvent_t next(Handle& h) {
     if (used == h.events.size()) {
@@ -380,8 +437,8 @@ struct StepTimer {
 // ---- fused passes (7-point stencil): S middle steps per launch
 
 template <class T, int S, int TY>
-static void launch_fused(const Handle& h, const T* ya, const T* yb, T* oa, T* ob, int j, const DevState* guard,
-                         hipStream_t s) {
+static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T* oa, T* ob, int j,
+                         const DevState* guard, hipStream_t s) {
   FusedCoef<typename Store<T>::acc, S> cf;
   for (int m = 0; m < S; ++m) {
     const Coef<T> c = step_coef<T>(h, j + m);
@@ -397,25 +454,26 @@ static void launch_fused(const Handle& h, const T* ya, const T* yb, T* oa, T* ob
   const int chunks = std::max(1, std::min<int>(max_chunks, int((1024 + xy - 1) / xy)));
   const int zc = (op.nz + chunks - 1) / chunks;
   const uint32_t ntiles = xy * uint32_t((op.nz + zc - 1) / zc);
-  k_stencil7_fused<S, TY, T><<<round_grid(ntiles), kBlock, 0, s>>>(
-      ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard);
+  k_stencil7_fused<S, TY, T><<<dim3(round_grid(ntiles), sl.count), kBlock, 0, s>>>(
+      ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard,
+      h.ldw, sl.first);
 }
 
 template <class T>
-static void launch_fused_any(const Handle& h, int S, const T* ya, const T* yb, T* oa, T* ob, int j,
+static void launch_fused_any(const Handle& h, Slots sl, int S, const T* ya, const T* yb, T* oa, T* ob, int j,
                              const DevState* guard, hipStream_t s) {
   if constexpr (sizeof(T) == 8) {
     if (S == 2)
-      launch_fused<T, 2, 8>(h, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 2, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
     else
-      launch_fused<T, 3, 4>(h, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 3, 4>(h, sl, ya, yb, oa, ob, j, guard, s);
   } else {
     if (S == 2)
-      launch_fused<T, 2, 8>(h, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 2, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
     else if (S == 3)
-      launch_fused<T, 3, 8>(h, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 3, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
     else
-      launch_fused<T, 4, 8>(h, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 4, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
   }
 }
 
@@ -427,14 +485,17 @@ static int effective_fuse(const Handle& h) {
   return ok ? h.fuse : 1;
 }
 
-// Steps 1..k of Alg. 2 on the prepared input (s, y_0 = Y[0]); the last step
-// writes z in float64.  dots: reduce (r, z), (z, q) and form beta (inside a
-// solve).  Middle steps run S at a time when fusion is on.
+// Steps 1..k of Alg. 2 on the prepared input (s, y_0 = Y[0]) of the slots; the
+// last step writes z in float64.  Every vector has the workspace stride ldw
+// (a single slot 0 may pass the caller's r and z: its offset is zero).
+// dots: reduce (r, z), (z, q) and form beta (inside a solve).  Middle steps
+// run S at a time when fusion is on.
 template <class T>
-static void enqueue_steps(Handle& h, double* z, const double* r, const double* q, bool dots, int init, int flexible,
-                          DevState* guard, StepTimer* timer, hipStream_t s) {
+static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const double* q, bool dots, int init,
+                          int flexible, DevState* guard, StepTimer* timer, hipStream_t s) {
   const int k = h.prm.k;
   const int S = effective_fuse(h);
+  const int64_t ldw = h.ldw;
   T* Y[4] = {reinterpret_cast<T*>(h.Y[0]), reinterpret_cast<T*>(h.Y[1]), reinterpret_cast<T*>(h.Y[2]),
              reinterpret_cast<T*>(h.Y[3])};
   const T* sv = reinterpret_cast<const T*>(h.s);
@@ -448,29 +509,34 @@ static void enqueue_steps(Handle& h, double* z, const double* r, const double* q
     if (timer && k >= 3 && j == 2) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
     const T* yin = Y[cur];
     const T* yprev = prev >= 0 ? Y[prev] : nullptr;
+    const InVec<T> in{yin, ldw};
     if (j == k) {
       const Coef<T> c = step_coef<T>(h, j);
       if (j == 1) {
         if (dots)
-          launch_bop<T>(h, InVec<T>{yin},
-                        EpiChebLast<T, true, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, flexible}, s);
+          launch_bop<T>(h, in, EpiChebLast<T, true, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init,
+                                                          flexible, ldw},
+                        sl.first, sl.count, s);
         else
-          launch_bop<T>(h, InVec<T>{yin},
-                        EpiChebLast<T, true, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0}, s);
+          launch_bop<T>(h, in, EpiChebLast<T, true, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0,
+                                                           ldw},
+                        sl.first, sl.count, s);
       } else {
         if (dots)
-          launch_bop<T>(h, InVec<T>{yin},
-                        EpiChebLast<T, false, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, flexible}, s);
+          launch_bop<T>(h, in, EpiChebLast<T, false, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init,
+                                                           flexible, ldw},
+                        sl.first, sl.count, s);
         else
-          launch_bop<T>(h, InVec<T>{yin},
-                        EpiChebLast<T, false, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0}, s);
+          launch_bop<T>(h, in, EpiChebLast<T, false, false>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init, 0,
+                                                            ldw},
+                        sl.first, sl.count, s);
       }
       break;
     }
     if (j >= 2 && S >= 2 && j + S - 1 <= k - 1) {
       const int ob = free_buf(-1);
       const int oa = free_buf(ob);
-      launch_fused_any<T>(h, S, yin, yprev, Y[oa], Y[ob], j, guard, s);
+      launch_fused_any<T>(h, sl, S, yin, yprev, Y[oa], Y[ob], j, guard, s);
       prev = ob;
       cur = oa;
       j += S;
@@ -478,9 +544,11 @@ static void enqueue_steps(Handle& h, double* z, const double* r, const double* q
       const int o = free_buf(-1);
       const Coef<T> c = step_coef<T>(h, j);
       if (j == 1)
-        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, true>{yprev, sv, Y[o], c.a, c.b, c.c, nullptr, guard}, s);
+        launch_bop<T>(h, in, EpiChebStep<T, true>{yprev, sv, Y[o], c.a, c.b, c.c, nullptr, guard, ldw}, sl.first,
+                      sl.count, s);
       else
-        launch_bop<T>(h, InVec<T>{yin}, EpiChebStep<T, false>{yprev, sv, Y[o], c.a, c.b, c.c, nullptr, guard}, s);
+        launch_bop<T>(h, in, EpiChebStep<T, false>{yprev, sv, Y[o], c.a, c.b, c.c, nullptr, guard, ldw}, sl.first,
+                      sl.count, s);
       prev = cur;
       cur = o;
       ++j;
@@ -489,16 +557,18 @@ static void enqueue_steps(Handle& h, double* z, const double* r, const double* q
   }
 }
 
+// Stand-alone application r -> z (caller vectors) on slot 0 of the workspace.
 template <class T>
-static void enqueue_apply(Handle& h, const double* r, double* z, hipStream_t s) {
+static void enqueue_apply_one(Handle& h, const double* r, double* z, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
-    k_jacobi<<<pair_grid(n), kBlock, 0, s>>>(r, z, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr, h.rb(), 0, 0);
+    k_jacobi<<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, z, 0, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr,
+                                                      h.rb(), 0, 0, 0);
     return;
   }
-  k_prep<T><<<pair_grid(n), kBlock, 0, s>>>(r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
-                                           1.0 / h.theta, n, nullptr);
-  enqueue_steps<T>(h, z, r, nullptr, false, 0, 0, nullptr, nullptr, s);
+  k_prep<T><<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]),
+                                                     h.ldw, invdiag(h), 1.0 / h.theta, n, nullptr, 0);
+  enqueue_steps<T>(h, Slots{0, 1}, z, r, nullptr, false, 0, 0, nullptr, nullptr, s);
 }
 
 #define PCHEB_BY_PREC(h, FN, ...)                      \
@@ -656,28 +726,37 @@ void setup_operator(Handle& h, hipStream_t s) {
   if (bad_host) fail(PCHEB_NOT_SPD, "operator has a non-positive diagonal entry or coefficient");
 }
 
-// Recurrence scalars, the scaled operator copies and the solve workspace.
+// Recurrence scalars and the scaled operator copies.
 static void setup_preconditioner(Handle& h, hipStream_t s) {
-  const int64_t n = h.n;
   chebyshev_scalars(h);
   h.elem = storage_bytes(h.prm.prec);
   PCHEB_BY_PREC(h, build_scaled_values, h, s);
-
   h.fuse = std::max(1, std::min(h.prm.fuse_steps, h.prm.prec == PCHEB_F64 ? 3 : 4));
   h.nY = (h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2) ? 4 : 3;
-  h.s = dev_alloc(h, size_t(n) * h.elem);
-  for (int i = 0; i < h.nY; ++i) h.Y[i] = dev_alloc(h, size_t(n) * h.elem);
-  h.r = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
-  h.p[0] = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
-  h.p[1] = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
-  h.q = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
-  h.z = static_cast<double*>(dev_alloc(h, size_t(n) * 8));
-  h.st = static_cast<DevState*>(dev_alloc(h, sizeof(DevState)));
-  h.partials = static_cast<double*>(dev_alloc(h, size_t(kMaxGrid) * kMaxReduce * sizeof(double)));
-  PCHEB_HIP_CHECK(hipMemsetAsync(h.st, 0, sizeof(DevState), s));
-  PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h.st_host), 2 * sizeof(DevState), hipHostMallocDefault));
-  std::memset(h.st_host, 0, 2 * sizeof(DevState));
-  PCHEB_HIP_CHECK(hipStreamSynchronize(s));
+  h.ldw = round_up(h.n, 64);
+}
+
+// Solve workspace for `cap` slots (reallocated when a call needs more).
+void ensure_workspace(Handle& h, int cap) {
+  if (cap <= h.cap) return;
+  release_workspace(h);
+  const size_t lw = size_t(h.ldw) * size_t(cap);
+  auto& ws = h.owned_ws;
+  h.s = alloc_into(ws, lw * h.elem);
+  for (int i = 0; i < h.nY; ++i) h.Y[i] = alloc_into(ws, lw * h.elem);
+  for (int i = h.nY; i < 4; ++i) h.Y[i] = nullptr;
+  h.r = static_cast<double*>(alloc_into(ws, lw * 8));
+  h.p[0] = static_cast<double*>(alloc_into(ws, lw * 8));
+  h.p[1] = static_cast<double*>(alloc_into(ws, lw * 8));
+  h.q = static_cast<double*>(alloc_into(ws, lw * 8));
+  h.z = static_cast<double*>(alloc_into(ws, lw * 8));
+  h.st = static_cast<DevState*>(alloc_into(ws, size_t(cap) * sizeof(DevState)));
+  h.partials = static_cast<double*>(alloc_into(ws, size_t(cap) * kMaxGrid * kMaxReduce * sizeof(double)));
+  PCHEB_HIP_CHECK(hipMemset(h.st, 0, size_t(cap) * sizeof(DevState)));
+  PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h.st_host), 2 * size_t(cap) * sizeof(DevState),
+                                hipHostMallocDefault));
+  std::memset(h.st_host, 0, 2 * size_t(cap) * sizeof(DevState));
+  h.cap = cap;
 }
 
 static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs) {
@@ -692,67 +771,106 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
   }
   if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 4 : 0);
   const int ny = (A->kind == PCHEB_OP_STENCIL7 && p->fuse_steps >= 2) ? 4 : 3;
-  const size_t per_rhs = size_t(n) * ((1 + ny) * e + 5 * 8);
-  b += size_t(std::max(1, nrhs)) * per_rhs;
-  b += size_t(kMaxGrid) * kMaxReduce * 8 + sizeof(DevState) + 256;
+  const size_t per_rhs = size_t(round_up(n, 64)) * ((1 + ny) * e + 5 * 8) + sizeof(DevState) +
+                         size_t(kMaxGrid) * kMaxReduce * 8;
+  b += size_t(std::max(1, nrhs)) * per_rhs + 256;
   return b;
 }
 
-// ================================================================ PCG driver
+// ================================================================ PCG internals (slot ranges)
+
+__global__ void k_init_states(DevState* st, int slot0, int count, double tol, int maxit, int flexible) {
+  const int i = int(threadIdx.x);
+  if (i >= count) return;
+  DevState d{};
+  d.tol = tol;
+  d.maxit = maxit;
+  d.flexible = flexible;
+  st[slot0 + i] = d;
+}
+
+// Slots that must not take part in a launch over a wider range are marked done.
+__global__ void k_retire_states(DevState* st, int slot0, int count) {
+  const int i = int(threadIdx.x);
+  if (i < count && st[slot0 + i].done == kRunning) st[slot0 + i].done = kMaxIter;
+}
 
 template <class T>
-static void enqueue_prep_or_jacobi(Handle& h, int init, int flexible, StepTimer* timer, hipStream_t s) {
+static void enqueue_precond(Handle& h, Slots sl, int init, int flexible, StepTimer* timer, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
     const uint32_t g = pair_grid(n);
-    k_jacobi<<<g, kBlock, 0, s>>>(h.r, h.z, h.q, invdiag(h), 1.0 / h.theta, n, h.st, h.rb(), 1, flexible);
-    k_finalize<2, FinBeta><<<1, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st);
+    k_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, invdiag(h), 1.0 / h.theta, n, h.st,
+                                                  h.rb(), 1, flexible, sl.first);
+    k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
     return;
   }
-  k_prep<T><<<pair_grid(n), kBlock, 0, s>>>(h.r, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), invdiag(h),
-                                           1.0 / h.theta, n, h.st);
-  enqueue_steps<T>(h, h.z, h.r, h.q, true, init, flexible, h.st, timer, s);
+  k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(h.r, h.ldw, reinterpret_cast<T*>(h.s),
+                                                            reinterpret_cast<T*>(h.Y[0]), h.ldw, invdiag(h),
+                                                            1.0 / h.theta, n, h.st, sl.first);
+  enqueue_steps<T>(h, sl, h.z, h.r, h.q, true, init, flexible, h.st, timer, s);
 }
 
-// One PCG iteration: q = A (z + beta p_old), the update with the fused
-// preconditioner input, and the k recurrence steps (beta formed on the device).
 template <class T>
-static void enqueue_iteration(Handle& h, double* x, const double* b, int cur, int flexible, bool refresh,
-                              StepTimer* timer, hipStream_t s) {
+static void enqueue_start(Handle& h, Slots sl, const double* b, int64_t ldb, double* x, int64_t ldx, bool x0_given,
+                          int flexible, StepTimer* timer, hipStream_t s) {
+  const int64_t n = h.n;
+  if (x0_given) {
+    k_zero_slots<<<dim3(flat_grid(n), sl.count), kBlock, 0, s>>>(h.p[0], h.ldw, n, sl.first);
+    launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, h.r, invdiag(h), h.st, nullptr, 0, ldb, h.ldw}, sl.first,
+                sl.count, s);
+  } else {
+    const uint32_t g = pair_grid(n);
+    k_start_zero<<<dim3(g, sl.count), kBlock, 0, s>>>(b, ldb, x, ldx, h.r, h.p[0], h.ldw, invdiag(h), n, h.rb(),
+                                                      sl.first);
+    k_finalize<2, FinStart><<<sl.count, kBlock, 0, s>>>(FinStart{h.st}, h.rb(), g, nullptr, sl.first);
+  }
+  enqueue_precond<T>(h, sl, 1, flexible, timer, s);
+}
+
+// One PCG iteration on the slots: q = A (z + beta p_old), the update with the
+// fused preconditioner input, and the k recurrence steps (beta formed on the device).
+template <class T>
+static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const double* b, int64_t ldb, int cur,
+                              int flexible, bool refresh, StepTimer* timer, hipStream_t s) {
   const int64_t n = h.n;
   DevState* st = h.st;
   double* p_new = h.p[cur ^ 1];
-  launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0}, EpiDirection{p_new, h.q, st, st}, s);
+  launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0, h.ldw}, EpiDirection{p_new, h.q, st, st, h.ldw}, sl.first,
+              sl.count, s);
   const uint32_t g = pair_grid(n);
+  const dim3 grid(g, sl.count);
   if (refresh) {
-    k_update<T, 2><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), nullptr, nullptr, nullptr, 0.0, n, st,
-                                        h.rb());
-    k_finalize<3, FinUpdate<2>><<<1, kBlock, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st);
-    launch_ahat(h, InVec<double>{x}, EpiResidual{b, h.r, invdiag(h), st, st, 2}, s);
-    enqueue_prep_or_jacobi<T>(h, 0, flexible, timer, s);
+    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
+                                           n, st, h.rb(), sl.first);
+    k_finalize<3, FinUpdate<2>><<<sl.count, kBlock, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
+    launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, h.r, invdiag(h), st, st, 2, ldb, h.ldw}, sl.first, sl.count,
+                s);
+    enqueue_precond<T>(h, sl, 0, flexible, timer, s);
     return;
   }
   if (h.prm.k == 0) {
-    k_update<double, 1><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), nullptr, nullptr, h.z, 1.0 / h.theta, n,
-                                             st, h.rb());
-    k_finalize<3, FinUpdate<1>><<<1, kBlock, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st);
+    k_update<double, 1><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, h.z,
+                                                1.0 / h.theta, n, st, h.rb(), sl.first);
+    k_finalize<3, FinUpdate<1>><<<sl.count, kBlock, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st, sl.first);
   } else {
-    k_update<T, 0><<<g, kBlock, 0, s>>>(x, h.r, p_new, h.q, invdiag(h), reinterpret_cast<T*>(h.s),
-                                        reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb());
-    k_finalize<3, FinUpdate<0>><<<1, kBlock, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st);
-    enqueue_steps<T>(h, h.z, h.r, h.q, true, 0, flexible, st, timer, s);
+    k_update<T, 0><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), reinterpret_cast<T*>(h.s),
+                                           reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb(),
+                                           sl.first);
+    k_finalize<3, FinUpdate<0>><<<sl.count, kBlock, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st, sl.first);
+    enqueue_steps<T>(h, sl, h.z, h.r, h.q, true, 0, flexible, st, timer, s);
   }
 }
 
 template <class T>
-static void capture_pair(Handle& h, double* x, const double* b, int flexible) {
+static void capture_pair(Handle& h, Slots sl, double* x, int64_t ldx, int flexible) {
   if (!h.capture_stream) PCHEB_HIP_CHECK(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking));
   hipStream_t s = h.capture_stream;
   hipGraph_t graph = nullptr;
   PCHEB_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   try {
-    enqueue_iteration<T>(h, x, b, 0, flexible, false, nullptr, s);
-    enqueue_iteration<T>(h, x, b, 1, flexible, false, nullptr, s);
+    enqueue_iteration<T>(h, sl, x, ldx, nullptr, 0, 0, flexible, false, nullptr, s);
+    enqueue_iteration<T>(h, sl, x, ldx, nullptr, 0, 1, flexible, false, nullptr, s);
   } catch (...) {
     (void)hipStreamEndCapture(s, &graph);
     if (graph) (void)hipGraphDestroy(graph);
@@ -763,15 +881,86 @@ static void capture_pair(Handle& h, double* x, const double* b, int flexible) {
   const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   PCHEB_HIP_CHECK(e);
-  if (h.graph_exec) (void)hipGraphExecDestroy(h.graph_exec);
+  drop_graph(h);
   h.graph_exec = exec;
+  h.graph_x = x;
+  h.graph_ldx = ldx;
+  h.graph_slots = sl.first * 65536 + sl.count;
+  h.graph_flags = uint32_t(flexible);
 }
 
 template <class T>
-static pcheb_status solve_impl(Handle& h, const double* b, double* x, double tol, int maxit, uint32_t flags,
-                               pcg_stats* stats, hipStream_t s) {
+static void enqueue_pairs_graph(Handle& h, Slots sl, double* x, int64_t ldx, int pairs, int flexible, hipStream_t s) {
+  if (h.graph_exec == nullptr || h.graph_x != x || h.graph_ldx != ldx ||
+      h.graph_slots != sl.first * 65536 + sl.count || h.graph_flags != uint32_t(flexible))
+    capture_pair<T>(h, sl, x, ldx, flexible);
+  for (int i = 0; i < pairs; ++i) PCHEB_HIP_CHECK(hipGraphLaunch(h.graph_exec, s));
+}
+
+template <class T>
+static void enqueue_finish(Handle& h, Slots sl, const double* b, int64_t ldb, const double* x, int64_t ldx,
+                           hipStream_t s) {
+  launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, nullptr, invdiag(h), h.st, nullptr, 1, ldb, h.ldw}, sl.first,
+              sl.count, s);
+}
+
+// ---- exported to the serving engine (solver.hpp)
+
+void solver_init_states(Handle& h, Slots sl, double tol, int maxit, int flexible, hipStream_t s) {
+  k_init_states<<<1, std::max(1, sl.count), 0, s>>>(h.st, sl.first, sl.count, tol, maxit, flexible);
+  PCHEB_HIP_CHECK(hipGetLastError());
+}
+
+void solver_retire(Handle& h, Slots sl, hipStream_t s) {
+  k_retire_states<<<1, std::max(1, sl.count), 0, s>>>(h.st, sl.first, sl.count);
+  PCHEB_HIP_CHECK(hipGetLastError());
+}
+
+void solver_start(Handle& h, Slots sl, const double* b, int64_t ldb, double* x, int64_t ldx, bool x0_given,
+                  int flexible, hipStream_t s) {
+  PCHEB_BY_PREC(h, enqueue_start, h, sl, b, ldb, x, ldx, x0_given, flexible, nullptr, s);
+  PCHEB_HIP_CHECK(hipGetLastError());
+}
+
+void solver_iteration_pairs(Handle& h, Slots sl, double* x, int64_t ldx, int pairs, int flexible, hipStream_t s) {
+  PCHEB_BY_PREC(h, enqueue_pairs_graph, h, sl, x, ldx, pairs, flexible, s);
+  PCHEB_HIP_CHECK(hipGetLastError());
+}
+
+void solver_finish(Handle& h, Slots sl, const double* b, int64_t ldb, const double* x, int64_t ldx, hipStream_t s) {
+  PCHEB_BY_PREC(h, enqueue_finish, h, sl, b, ldb, x, ldx, s);
+  PCHEB_HIP_CHECK(hipGetLastError());
+}
+
+void fill_stats(const Handle& h, const DevState& fin, uint32_t flags, pcg_stats* stats) {
+  pcheb_status status = PCHEB_OK;
+  if (fin.done == kBreakdown)
+    status = PCHEB_BREAKDOWN;
+  else if (fin.done != kConverged)
+    status = PCHEB_NOT_CONVERGED;
+  pcg_stats& o = *stats;
+  std::memset(&o, 0, sizeof(o));
+  o.iters = fin.iter;
+  o.converged = fin.done == kConverged;
+  o.status = status;
+  o.relres = fin.relres;
+  o.relres_true = fin.bb > 0 ? std::sqrt(fin.true_rr) / std::sqrt(fin.bb) : 0.0;
+  o.relres_true_hat = fin.bb_hat > 0 ? std::sqrt(fin.true_rr_hat) / std::sqrt(fin.bb_hat) : 0.0;
+  const int64_t k = h.prm.k;
+  const int64_t applies =
+      fin.iter == 0 ? (fin.done == kConverged ? 0 : 1) : (fin.done == kMaxIter ? fin.iter + 1 : fin.iter);
+  o.n_spmv = fin.iter + k * applies + ((flags & PCG_X0_GIVEN) ? 1 : 0);
+  o.n_dot = applies + 2 * int64_t(fin.iter) + ((flags & PCG_FLEXIBLE) ? std::max<int64_t>(0, applies - 1) : 0);
+}
+
+// ================================================================ PCG driver
+
+template <class T>
+static pcheb_status solve_impl(Handle& h, const double* b, double* x, int nrhs, int64_t ld, double tol, int maxit,
+                               uint32_t flags, pcg_stats* stats, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  const int64_t n = h.n;
+  ensure_workspace(h, nrhs);
+  const Slots sl{0, nrhs};
   const int flexible = (flags & PCG_FLEXIBLE) ? 1 : 0;
   const bool timed = (flags & PCG_TIME_KERNELS) != 0;
   const bool refresh = (flags & PCG_REFRESH) != 0;
@@ -779,63 +968,51 @@ static pcheb_status solve_impl(Handle& h, const double* b, double* x, double tol
   StepTimer timer;
   StepTimer* tp = timed ? &timer : nullptr;
 
-  DevState init{};
-  init.tol = tol;
-  init.maxit = maxit;
-  init.flexible = flexible;
-  DevState* hs = h.st_host;
-  hs[0] = init;
-  PCHEB_HIP_CHECK(hipMemcpyAsync(h.st, &hs[0], sizeof(DevState), hipMemcpyHostToDevice, s));
-  if (flags & PCG_X0_GIVEN) {
-    k_fill<<<flat_grid(n), kBlock, 0, s>>>(h.p[0], n, 0.0);
-    launch_ahat(h, InVec<double>{x}, EpiResidual{b, h.r, invdiag(h), h.st, nullptr, 0}, s);
-  } else {
-    const uint32_t g = pair_grid(n);
-    k_start_zero<<<g, kBlock, 0, s>>>(b, x, h.r, h.p[0], invdiag(h), n, h.rb());
-    k_finalize<2, FinStart><<<1, kBlock, 0, s>>>(FinStart{h.st}, h.rb(), g, nullptr);
-  }
-  enqueue_prep_or_jacobi<T>(h, 1, flexible, tp, s);
+  solver_init_states(h, sl, tol, maxit, flexible, s);
+  enqueue_start<T>(h, sl, b, ld, x, ld, (flags & PCG_X0_GIVEN) != 0, flexible, tp, s);
   PCHEB_HIP_CHECK(hipGetLastError());
-
-  if (use_graph && (h.graph_exec == nullptr || h.graph_x != x || h.graph_flags != uint32_t(flexible))) {
-    capture_pair<T>(h, x, b, flexible);
-    h.graph_x = x;
-    h.graph_flags = uint32_t(flexible);
-  }
 
   int cur = 0;
   int64_t issued = 0;
   int chunk = 2;
-  int slot = 0;
+  int half = 0;
   bool have_prev = false;
+  DevState* hs = h.st_host;
+  auto all_done = [&](const DevState* v) {
+    for (int i = 0; i < nrhs; ++i)
+      if (v[i].done == kRunning) return false;
+    return true;
+  };
   hipEvent_t ev[2];
   PCHEB_HIP_CHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   PCHEB_HIP_CHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   try {
     for (;;) {
-      for (int it = 0; it < chunk; ++it) {
-        const bool ref = refresh && issued > 0 && (issued + 1) % 50 == 0;
-        if (use_graph) {
-          if (it % 2 == 0) PCHEB_HIP_CHECK(hipGraphLaunch(h.graph_exec, s));
-        } else {
-          enqueue_iteration<T>(h, x, b, cur, flexible, ref, tp, s);
+      if (use_graph) {
+        enqueue_pairs_graph<T>(h, sl, x, ld, chunk / 2, flexible, s);
+        issued += chunk;
+      } else {
+        for (int it = 0; it < chunk; ++it) {
+          const bool ref = refresh && issued > 0 && (issued + 1) % 50 == 0;
+          enqueue_iteration<T>(h, sl, x, ld, b, ld, cur, flexible, ref, tp, s);
           cur ^= 1;
+          ++issued;
         }
-        ++issued;
       }
       PCHEB_HIP_CHECK(hipGetLastError());
-      PCHEB_HIP_CHECK(hipMemcpyAsync(&hs[slot], h.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-      PCHEB_HIP_CHECK(hipEventRecord(ev[slot], s));
+      DevState* dst = hs + size_t(half) * nrhs;
+      PCHEB_HIP_CHECK(hipMemcpyAsync(dst, h.st, size_t(nrhs) * sizeof(DevState), hipMemcpyDeviceToHost, s));
+      PCHEB_HIP_CHECK(hipEventRecord(ev[half], s));
       if (have_prev) {
-        PCHEB_HIP_CHECK(hipEventSynchronize(ev[slot ^ 1]));
-        if (hs[slot ^ 1].done != kRunning) break;
+        PCHEB_HIP_CHECK(hipEventSynchronize(ev[half ^ 1]));
+        if (all_done(hs + size_t(half ^ 1) * nrhs)) break;
       }
       have_prev = true;
-      slot ^= 1;
+      half ^= 1;
       if (chunk < 16) chunk *= 2;
       if (issued > int64_t(maxit) + 64) {
         // the device stops at maxit; wait for the last copy and leave
-        PCHEB_HIP_CHECK(hipEventSynchronize(ev[slot ^ 1]));
+        PCHEB_HIP_CHECK(hipEventSynchronize(ev[half ^ 1]));
         break;
       }
     }
@@ -847,47 +1024,35 @@ static pcheb_status solve_impl(Handle& h, const double* b, double* x, double tol
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
 
-  // true residual at exit
-  launch_ahat(h, InVec<double>{x}, EpiResidual{b, nullptr, invdiag(h), h.st, nullptr, 1}, s);
+  enqueue_finish<T>(h, sl, b, ld, x, ld, s);
   PCHEB_HIP_CHECK(hipGetLastError());
-  PCHEB_HIP_CHECK(hipMemcpyAsync(&hs[0], h.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  PCHEB_HIP_CHECK(hipMemcpyAsync(hs, h.st, size_t(nrhs) * sizeof(DevState), hipMemcpyDeviceToHost, s));
   PCHEB_HIP_CHECK(hipStreamSynchronize(s));
-  const DevState fin = hs[0];
 
-  pcheb_status status = PCHEB_OK;
-  if (fin.done == kBreakdown)
-    status = PCHEB_BREAKDOWN;
-  else if (fin.done != kConverged)
-    status = PCHEB_NOT_CONVERGED;
-  if (stats) {
-    pcg_stats& o = *stats;
-    std::memset(&o, 0, sizeof(o));
-    o.iters = fin.iter;
-    o.converged = fin.done == kConverged;
-    o.status = status;
-    o.relres = fin.relres;
-    o.relres_true = fin.bb > 0 ? std::sqrt(fin.true_rr) / std::sqrt(fin.bb) : 0.0;
-    o.relres_true_hat = fin.bb_hat > 0 ? std::sqrt(fin.true_rr_hat) / std::sqrt(fin.bb_hat) : 0.0;
-    const int64_t k = h.prm.k;
-    const int64_t applies = fin.iter == 0 ? (fin.done == kConverged ? 0 : 1)
-                                          : (fin.done == kMaxIter ? fin.iter + 1 : fin.iter);
-    o.n_spmv = fin.iter + k * applies + ((flags & PCG_X0_GIVEN) ? 1 : 0);
-    o.n_dot = applies + 2 * int64_t(fin.iter) + (flexible ? std::max<int64_t>(0, applies - 1) : 0);
-    if (timed && h.prm.k >= 3) {
-      // applications that ran: the initial one plus one per non-final iteration
-      const size_t pairs = std::min(timer.used / 2, size_t(applies));
-      double ms = 0.0;
-      for (size_t i = 0; i < pairs; ++i) {
-        float t = 0.f;
-        PCHEB_HIP_CHECK(hipEventElapsedTime(&t, h.events[2 * i], h.events[2 * i + 1]));
-        ms += t;
-      }
-      o.step_ms = ms;
-      o.step_launches = int64_t(pairs) * (h.prm.k - 2);
-    }
-    o.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // the slowest right-hand side decides the reported statistics and status
+  int worst = 0;
+  for (int i = 1; i < nrhs; ++i) {
+    const bool bad_i = hs[i].done != kConverged, bad_w = hs[worst].done != kConverged;
+    if ((bad_i && !bad_w) || (bad_i == bad_w && hs[i].iter > hs[worst].iter)) worst = i;
   }
-  return status;
+  pcg_stats local;
+  fill_stats(h, hs[worst], flags, &local);
+  if (timed && h.prm.k >= 3 && nrhs == 1) {
+    // applications that ran: the initial one plus one per non-final iteration
+    const int64_t applies = local.n_spmv - local.iters;
+    const size_t pairs = std::min(timer.used / 2, size_t(applies / std::max(1, h.prm.k)));
+    double ms = 0.0;
+    for (size_t i = 0; i < pairs; ++i) {
+      float t = 0.f;
+      PCHEB_HIP_CHECK(hipEventElapsedTime(&t, h.events[2 * i], h.events[2 * i + 1]));
+      ms += t;
+    }
+    local.step_ms = ms;
+    local.step_launches = int64_t(pairs) * (h.prm.k - 2);
+  }
+  local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = local;
+  return pcheb_status(local.status);
 }
 
 }  // namespace pcheb
@@ -913,28 +1078,35 @@ static pcheb_status guarded(F&& f) {
   }
 }
 
-extern "C" {
+namespace pcheb {
 
-pcheb_status pcheb_setup(const pcheb_operator* A, const pcheb_params* p, hipStream_t stream, pcheb_handle* out) {
-  return guarded([&]() -> pcheb_status {
-    if (!out) fail(PCHEB_INVALID, "out is null");
-    validate(A, p);
-    Handle* h = new Handle();
-    h->op = *A;
-    h->prm = *p;
-    h->n = A->n;
-    try {
-      setup_operator(*h, stream);
-      setup_preconditioner(*h, stream);
-    } catch (...) {
-      release(*h);
-      delete h;
-      throw;
-    }
-    *out = reinterpret_cast<pcheb_handle>(h);
-    return PCHEB_OK;
-  });
+Handle* create_handle(const pcheb_operator* A, const pcheb_params* p, hipStream_t stream) {
+  validate(A, p);
+  Handle* h = new Handle();
+  h->op = *A;
+  h->prm = *p;
+  h->n = A->n;
+  try {
+    setup_operator(*h, stream);
+    setup_preconditioner(*h, stream);
+    ensure_workspace(*h, 1);
+  } catch (...) {
+    release(*h);
+    delete h;
+    throw;
+  }
+  return h;
 }
+
+void destroy_handle(Handle* h) {
+  if (!h) return;
+  release(*h);
+  delete h;
+}
+
+size_t footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs) { return footprint(A, p, nrhs); }
+
+}  // namespace pcheb
 
 static Handle* as_handle(pcheb_handle h) {
   if (!h) fail(PCHEB_INVALID, "null handle");
@@ -943,21 +1115,36 @@ static Handle* as_handle(pcheb_handle h) {
 
 static void check_vectors(const Handle& h, const void* a, const void* b, int32_t nrhs, int64_t ld) {
   if (!a || !b) fail(PCHEB_INVALID, "null vector");
-  if (nrhs != 1) fail(PCHEB_INVALID, "this build supports nrhs = 1");
+  if (nrhs < 1 || nrhs > 4096) fail(PCHEB_INVALID, "nrhs must be in [1, 4096]");
   if (ld < h.n) fail(PCHEB_INVALID, "ld must be >= n");
   if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) % 16 != 0)
     fail(PCHEB_INVALID, "vectors must be 16-byte aligned");
+  if (nrhs > 1 && ld % 2 != 0) fail(PCHEB_INVALID, "ld must be even when nrhs > 1 (16-byte aligned columns)");
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
-  const size_t bytes = size_t(h.n) * 8;
+  const size_t bytes = (size_t(nrhs - 1) * size_t(ld) + size_t(h.n)) * 8;
   if (pa < pb + bytes && pb < pa + bytes) fail(PCHEB_INVALID, "input and output vectors overlap");
+}
+
+extern "C" {
+
+pcheb_status pcheb_setup(const pcheb_operator* A, const pcheb_params* p, hipStream_t stream, pcheb_handle* out) {
+  return guarded([&]() -> pcheb_status {
+    if (!out) fail(PCHEB_INVALID, "out is null");
+    *out = reinterpret_cast<pcheb_handle>(create_handle(A, p, stream));
+    return PCHEB_OK;
+  });
 }
 
 pcheb_status pcheb_apply(pcheb_handle hh, const double* r, double* z, int32_t nrhs, int64_t ld, hipStream_t stream) {
   return guarded([&]() -> pcheb_status {
     Handle& h = *as_handle(hh);
     check_vectors(h, r, z, nrhs, ld);
-    PCHEB_BY_PREC(h, enqueue_apply, h, r, z, stream);
+    for (int32_t j = 0; j < nrhs; ++j) {
+      const double* rj = r + int64_t(j) * ld;
+      double* zj = z + int64_t(j) * ld;
+      PCHEB_BY_PREC(h, enqueue_apply_one, h, rj, zj, stream);
+    }
     PCHEB_HIP_CHECK(hipGetLastError());
     return PCHEB_OK;
   });
@@ -967,7 +1154,7 @@ pcheb_status pcheb_matvec(pcheb_handle hh, const double* x, double* y, int32_t n
   return guarded([&]() -> pcheb_status {
     Handle& h = *as_handle(hh);
     check_vectors(h, x, y, nrhs, ld);
-    launch_ahat(h, InVec<double>{x}, EpiStore<double>{y, nullptr, nullptr}, stream);
+    launch_ahat(h, InVec<double>{x, ld}, EpiStore<double>{y, nullptr, nullptr, ld}, 0, nrhs, stream);
     PCHEB_HIP_CHECK(hipGetLastError());
     return PCHEB_OK;
   });
@@ -983,13 +1170,13 @@ pcheb_status pcg_solve(pcheb_handle hh, const double* b, double* x, int32_t nrhs
     pcheb_status st = PCHEB_OK;
     switch (h.prm.prec) {
       case PCHEB_F64:
-        st = solve_impl<double>(h, b, x, tol, maxit, flags, stats, stream);
+        st = solve_impl<double>(h, b, x, nrhs, ld, tol, maxit, flags, stats, stream);
         break;
       case PCHEB_F32:
-        st = solve_impl<float>(h, b, x, tol, maxit, flags, stats, stream);
+        st = solve_impl<float>(h, b, x, nrhs, ld, tol, maxit, flags, stats, stream);
         break;
       default:
-        st = solve_impl<bf16>(h, b, x, tol, maxit, flags, stats, stream);
+        st = solve_impl<bf16>(h, b, x, nrhs, ld, tol, maxit, flags, stats, stream);
         break;
     }
     if (st == PCHEB_BREAKDOWN) set_last_error("PCG breakdown: (p, Ap) <= 0, (r, z) <= 0 or a non-finite value");
@@ -1000,15 +1187,12 @@ pcheb_status pcg_solve(pcheb_handle hh, const double* b, double* x, int32_t nrhs
 
 pcheb_status pcheb_destroy(pcheb_handle hh) {
   return guarded([&]() -> pcheb_status {
-    if (!hh) return PCHEB_OK;
-    Handle* h = reinterpret_cast<Handle*>(hh);
-    release(*h);
-    delete h;
+    destroy_handle(reinterpret_cast<Handle*>(hh));
     return PCHEB_OK;
   });
 }
 
-const char* pcheb_last_error(void) { return g_last_error.c_str(); }
+const char* pcheb_last_error(void) { return last_error_cstr(); }
 
 size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs) {
   if (!A || !p) return 0;

@@ -28,7 +28,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
-                 "pcheb_footprint_bytes", "pcheb_estimate_bounds"):
+                 "pcheb_footprint_bytes", "pcheb_estimate_bounds", "pserve_create", "pserve_submit", "pserve_poll",
+                 "pserve_wait", "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         assert name in fns
 
 
@@ -42,6 +43,10 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, f)
 
 
+STRUCTS = (("pcheb_operator", _abi.COperator), ("pcheb_params", _abi.CParams), ("pcg_stats", _abi.CStats),
+           ("pserve_request", _abi.CServeRequest), ("pserve_stats", _abi.CServeStats))
+
+
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc missing")
 def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
@@ -49,19 +54,15 @@ def test_struct_layout_matches_c(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "pcheb.h"\n'
         "#define O(T, f) printf(#T \".\" #f \" %zu\\n\", offsetof(T, f))\n"
         "int main(void) {\n"
-        ' printf("pcheb_operator %zu\\npcheb_params %zu\\npcg_stats %zu\\n", sizeof(pcheb_operator),'
-        " sizeof(pcheb_params), sizeof(pcg_stats));\n"
-        + "".join(f" O(pcheb_operator, {f});\n" for f, _ in _abi.COperator._fields_)
-        + "".join(f" O(pcheb_params, {f});\n" for f, _ in _abi.CParams._fields_)
-        + "".join(f" O(pcg_stats, {f});\n" for f, _ in _abi.CStats._fields_)
+        + "".join(f' printf("{c} %zu\\n", sizeof({c}));\n' for c, _ in STRUCTS)
+        + "".join(f" O({c}, {f});\n" for c, cls in STRUCTS for f, _ in cls._fields_)
         + " return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
                     str(src), "-o", str(exe)], check=True)
     lines = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True,
                                                                 text=True).stdout.splitlines())
-    for cname, cls in (("pcheb_operator", _abi.COperator), ("pcheb_params", _abi.CParams),
-                       ("pcg_stats", _abi.CStats)):
+    for cname, cls in STRUCTS:
         assert int(lines[cname]) == ctypes.sizeof(cls)
         for f, _ in cls._fields_:
             assert int(lines[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
@@ -106,6 +107,25 @@ def test_null_arguments():
     assert lib.pcheb_destroy(None) == 0
     lo, hi = ctypes.c_double(), ctypes.c_double()
     assert lib.pcheb_estimate_bounds(None, None, 30, ctypes.byref(lo), ctypes.byref(hi), None) == 1
+
+
+def test_server_argument_checks():
+    lib = pc.load_library()
+    out = ctypes.c_void_p()
+    assert lib.pserve_create(1 << 30, 0, ctypes.byref(out)) == 1 and "max_nrhs" in pc.pcheb_last_error()
+    assert lib.pserve_create(1 << 30, 65, ctypes.byref(out)) == 1
+    assert lib.pserve_create(0, 4, ctypes.byref(out)) == 1 and "budget" in pc.pcheb_last_error()
+    assert lib.pserve_create(1 << 30, 4, None) == 1
+    rid = ctypes.c_uint64()
+    assert lib.pserve_submit(None, None, ctypes.byref(rid)) == 1 and "server" in pc.pcheb_last_error()
+    assert lib.pserve_poll(None, 1, None, None) == 1
+    assert lib.pserve_wait(None, 1, None) == 1
+    assert lib.pserve_cancel(None, 1) == 1
+    assert lib.pserve_get_stats(None, None) == 1
+    assert lib.pserve_destroy(None) == 0
+    assert lib.pcheb_fill_uniform(None, -1, 0, 0.0, 1.0, None) == 1
+    assert lib.pcheb_fill_uniform(None, 5, 0, 0.0, 1.0, None) == 1
+    assert lib.pcheb_fill_uniform(8, 5, 0, 1.0, 0.0, None) == 1 and "lo <= hi" in pc.pcheb_last_error()
 
 
 def test_footprint_scales_with_precision_and_rhs():

@@ -292,3 +292,51 @@ def test_fused_solve_matches_oracle(pc, prec, S):
     assert st["relres_true"] <= TRUE_RES
     assert st2["iters"] == st["iters"] and torch.equal(x, x2)
     assert st2["step_launches"] == (k - 2) * st2["iters"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name", ["st7", "h27", "csr7", "sell_el"])
+def test_batched_solve_equals_single_solves(pc, name, prec):
+    """nrhs right-hand sides in one batched solve give each one exactly its single-solve result."""
+    c = case(name)
+    k = 7
+    n = c.n
+    ld = n + (n % 2)  # columns 16-byte aligned
+    rhs = [W.uniform(100 + j, n, -1.0, 1.0) for j in range(3)] + [np.zeros(n)]
+    B = torch.zeros((len(rhs), ld), dtype=torch.float64, device=DEV)
+    for j, r in enumerate(rhs):
+        B[j, :n] = _t(r)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.001, prec, fuse_steps=2) as h:
+        X = torch.full_like(B, float("nan"))
+        stb = pc.pcg_solve(h, B[:, :n], X[:, :n], flexible=True)
+        singles = []
+        for j in range(len(rhs)):
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            st = pc.pcg_solve(h, B[j, :n].contiguous(), x, flexible=True)
+            singles.append((st, x))
+    assert stb["status"] == "OK"
+    assert stb["iters"] == max(s[0]["iters"] for s in singles)
+    for j, (st, x) in enumerate(singles):
+        assert torch.equal(X[j, :n], x), (name, prec, j)
+    assert float(X[-1, :n].abs().max()) == 0.0 and singles[-1][0]["iters"] == 0
+
+
+def test_batched_apply_and_matvec(pc):
+    c = case("csr7")
+    n = c.n
+    ld = n + (n % 2)  # odd n: pad rows so every column stays 16-byte aligned
+    R = torch.zeros((3, ld), dtype=torch.float64, device=DEV)
+    for j in range(3):
+        R[j, :n] = _t(W.uniform(200 + j, n, -1.0, 1.0))
+    R = R[:, :n]
+    with pc.pcheb_setup(c.operator(torch, DEV), 5, c.lo, c.hi, 1.001, "f64") as h:
+        Z = torch.empty((3, ld), dtype=torch.float64, device=DEV)[:, :n]
+        pc.pcheb_apply(h, R, Z)
+        Y = torch.empty((3, ld), dtype=torch.float64, device=DEV)[:, :n]
+        pc.pcheb_matvec(h, R, Y)
+        torch.cuda.synchronize()
+    a = oracle.csr(c.rp, c.ci, c.v)
+    for j in range(3):
+        r = R[j].cpu().numpy()
+        assert rel_inf(Z[j].cpu().numpy(), oracle.nc_apply_unscaled(c.rp, c.ci, c.v, r, c.lo, c.hi, 5, 1.001)) <= 1e-11
+        assert rel_inf(Y[j].cpu().numpy(), a @ r) <= 1e-13

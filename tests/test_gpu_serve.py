@@ -1,0 +1,219 @@
+"""The solve server (pserve_* through the C ABI) on the GPU.
+
+A request's result must not depend on what else is being solved: each one is
+compared bit for bit with a single pcg_solve of the same right-hand side
+(flexible beta, x0 = 0, same parameters), which the parity tests tie to the
+oracle; one mix is also compared with the oracle directly.  Admission, budget
+rejection, eviction, cancellation, iteration limits and the statistics are
+checked on small problems.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import case, manufactured_rhs, oracle_solve
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+GiB = 1 << 30
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import paper_2008_01440_amd as pc
+    pc.load_library()
+    return pc
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _single(pc, op, c, b, k, prec, fuse, tol=1e-8, maxit=100000, bounds=None):
+    lo, hi = bounds if bounds else (c.lo, c.hi)
+    with pc.pcheb_setup(op, k, lo, hi, 1.001, prec, fuse_steps=fuse) as h:
+        x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st = pc.pcg_solve(h, b, x, tol=tol, maxit=maxit, flexible=True)
+    return st, x
+
+
+@pytest.mark.parametrize("seed,n,lo,hi", [(7, 1000, 0.5, 1.5), (3, 100003, -1.0, 1.0),
+                                          (2 ** 63 + 5, 17, -3.0, 7.0), (0, 0, 0.0, 1.0)])
+def test_fill_uniform_matches_host_generator(pc, seed, n, lo, hi):
+    v = torch.full((n,), float("nan"), dtype=torch.float64, device=DEV)
+    pc.pcheb_fill_uniform(v, seed, lo, hi)
+    torch.cuda.synchronize()
+    assert torch.equal(v.cpu(), torch.from_numpy(W.uniform(seed, n, lo, hi)))
+
+
+@pytest.mark.parametrize("max_nrhs", [1, 3, 8])
+def test_mixed_requests_equal_single_solves(pc, max_nrhs):
+    """Two operators, three precisions, more requests than slots: every result is
+    bitwise the single-solve result and the iteration counts agree."""
+    specs = []  # (case name, k, prec, fuse, seed)
+    for j in range(7):
+        specs.append(("st7", 6, ["f64", "f32", "bf16"][j % 3], 2, 300 + j))
+    for j in range(4):
+        specs.append(("h27", 9, "f32", 1, 400 + j))
+    ops = {name: case(name).operator(torch, DEV) for name in ("st7", "h27")}
+    bs, xs, ids = [], [], []
+    with pc.Server(4 * GiB, max_nrhs) as srv:
+        for name, k, prec, fuse, seed in specs:
+            c = case(name)
+            b = _t(W.uniform(seed, c.n, -1.0, 1.0))
+            x = torch.full((c.n,), float("nan"), dtype=torch.float64, device=DEV)
+            ids.append(srv.submit(ops[name], b, x, k, tol=1e-8, prec=prec, lambda_min=c.lo, lambda_max=c.hi,
+                                  fuse_steps=fuse))
+            bs.append(b)
+            xs.append(x)
+        stats = [srv.wait(i) for i in ids]
+        sv = srv.stats()
+    n = len(specs)
+    assert sv["submitted"] == n and sv["admitted"] == n and sv["completed"] == n and sv["rejected"] == 0
+    assert sv["groups_created"] == 4  # (st7, f64), (st7, f32), (st7, bf16), (h27, f32)
+    assert sum(sv["batch_hist"]) == sv["launches"]
+    assert all(h == 0 for h in sv["batch_hist"][int(np.ceil(np.log2(max_nrhs))) + 1:])
+    for (name, k, prec, fuse, _), b, x, st in zip(specs, bs, xs, stats):
+        c = case(name)
+        st1, x1 = _single(pc, ops[name], c, b, k, prec, fuse)
+        assert st["status"] == "OK" and st["iters"] == st1["iters"], (name, prec, st, st1)
+        assert torch.equal(x, x1), (name, prec, max_nrhs)
+        assert st["relres_true"] == st1["relres_true"] and st["seconds"] > 0
+
+
+def test_served_solution_matches_oracle(pc):
+    c = case("st7")
+    k, s = 10, 1.001
+    _, b = manufactured_rhs("st7")
+    ref = oracle_solve("st7", k, s, True)
+    with pc.Server(GiB, 4) as srv:
+        x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st = srv.wait(srv.submit(c.operator(torch, DEV), _t(b), x, k, tol=1e-8, prec="f64", lambda_min=c.lo,
+                                 lambda_max=c.hi, theta_scale=s))
+    diff = np.linalg.norm(x.cpu().numpy() - ref.x_hat) / np.linalg.norm(ref.x_hat)
+    assert st["status"] == "OK" and abs(st["iters"] - ref.iters) <= 1 and diff <= 1e-8
+
+
+def test_estimated_bounds_equal_explicit_estimate(pc):
+    """lambda_max <= 0: 30 Lanczos steps from SplitMix64 U[0.5, 1.5) with seed 7, widened
+    by 1.01 -- the same bounds the caller gets from pcheb_estimate_bounds."""
+    c = case("h27")
+    op = c.operator(torch, DEV)
+    lo, hi = pc.pcheb_estimate_bounds(op, _t(W.uniform(7, c.n, 0.5, 1.5)), 30)
+    b = _t(W.uniform(11, c.n, -1.0, 1.0))
+    st1, x1 = _single(pc, op, c, b, 8, "f64", 1, bounds=(lo, 1.01 * hi))
+    with pc.Server(GiB, 2) as srv:
+        x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st = srv.wait(srv.submit(op, b, x, 8, prec="f64"))
+    assert st["status"] == "OK" and st["iters"] == st1["iters"]
+    assert torch.equal(x, x1)
+
+
+def test_budget_rejects_oversized_request(pc):
+    c = case("st7_cube")
+    op = c.operator(torch, DEV)
+    b = torch.ones(c.n, dtype=torch.float64, device=DEV)
+    x = torch.zeros_like(b)
+    with pc.Server(1 << 20, 4) as srv:
+        with pytest.raises(pc.PchebError) as e:
+            srv.submit(op, b, x, 5, lambda_min=c.lo, lambda_max=c.hi)
+        assert e.value.name == "BUDGET"
+        sv = srv.stats()
+    assert sv["submitted"] == 1 and sv["rejected"] == 1 and sv["admitted"] == 0
+
+
+def test_eviction_under_budget(pc):
+    """A budget that holds one group: the second operator evicts the idle first one."""
+    ca, cb = case("st7"), case("csr7")
+    opa, opb = ca.operator(torch, DEV), cb.operator(torch, DEV)
+    need = max(pc.pcheb_footprint_bytes(opa, 5, prec="f64", nrhs=2),
+               pc.pcheb_footprint_bytes(opb, 5, prec="f64", nrhs=2))
+    budget = int(1.5 * need) + 4 * 8 * max(ca.n, cb.n) + 4096
+    with pc.Server(budget, 2) as srv:
+        ba = _t(W.uniform(21, ca.n, -1.0, 1.0))
+        xa = torch.zeros(ca.n, dtype=torch.float64, device=DEV)
+        sta = srv.wait(srv.submit(opa, ba, xa, 5, lambda_min=ca.lo, lambda_max=ca.hi))
+        bb = _t(W.uniform(22, cb.n, -1.0, 1.0))
+        xb = torch.zeros(cb.n, dtype=torch.float64, device=DEV)
+        stb = srv.wait(srv.submit(opb, bb, xb, 5, lambda_min=cb.lo, lambda_max=cb.hi))
+        sv = srv.stats()
+    assert sta["status"] == "OK" and stb["status"] == "OK"
+    assert sv["groups_created"] == 2 and sv["groups_evicted"] == 1 and sv["groups"] == 1
+    assert sv["bytes_high_water"] <= budget
+    assert torch.equal(xb, _single(pc, opb, cb, bb, 5, "f64", 1)[1])
+
+
+def test_cancel_leaves_others_intact(pc):
+    c = case("st7_cube")
+    op = c.operator(torch, DEV)
+    bs = [_t(W.uniform(500 + j, c.n, -1.0, 1.0)) for j in range(3)]
+    xs = [torch.zeros(c.n, dtype=torch.float64, device=DEV) for _ in range(3)]
+    with pc.Server(GiB, 4) as srv:
+        # the middle request would run for a long time without the cancel
+        ids = [srv.submit(op, bs[0], xs[0], 4, lambda_min=c.lo, lambda_max=c.hi),
+               srv.submit(op, bs[1], xs[1], 4, tol=1e-300, maxit=20000, lambda_min=c.lo, lambda_max=c.hi),
+               srv.submit(op, bs[2], xs[2], 4, lambda_min=c.lo, lambda_max=c.hi)]
+        srv.cancel(ids[1])
+        st = [srv.wait(i) for i in ids]
+        sv = srv.stats()
+        with pytest.raises(pc.PchebError) as e:
+            srv.poll(ids[0])  # reported ids are released
+        assert e.value.name == "NOT_FOUND"
+    assert st[1]["status"] == "NOT_CONVERGED" and sv["cancelled"] == 1 and sv["completed"] == 2
+    for j in (0, 2):
+        assert st[j]["status"] == "OK"
+        assert torch.equal(xs[j], _single(pc, op, c, bs[j], 4, "f64", 1)[1])
+
+
+def test_iteration_limit_and_zero_rhs(pc):
+    c = case("st7")
+    op = c.operator(torch, DEV)
+    b = _t(W.uniform(31, c.n, -1.0, 1.0))
+    x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+    z = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+    xz = torch.full((c.n,), 5.0, dtype=torch.float64, device=DEV)
+    with pc.Server(GiB, 4) as srv:
+        i1 = srv.submit(op, b, x, 3, maxit=3, lambda_min=c.lo, lambda_max=c.hi)
+        i2 = srv.submit(op, z, xz, 3, lambda_min=c.lo, lambda_max=c.hi)
+        st1, st2 = srv.wait(i1), srv.wait(i2)
+    st_ref, x_ref = _single(pc, op, c, b, 3, "f64", 1, maxit=3)
+    assert st1["status"] == "NOT_CONVERGED" and st1["iters"] == 3 == st_ref["iters"]
+    assert torch.equal(x, x_ref)
+    assert st2["status"] == "OK" and st2["iters"] == 0 and float(xz.abs().max()) == 0.0
+
+
+def test_invalid_operator_fails_its_request_only(pc):
+    c = case("st7")
+    good = c.operator(torch, DEV)
+    bad = pc.Operator.stencil7(*c.dims)
+    bad.c.n = c.n + 1  # inconsistent with nx*ny*nz: the group set-up rejects it
+    b = _t(W.uniform(41, c.n, -1.0, 1.0))
+    xb = torch.zeros(c.n + 1, dtype=torch.float64, device=DEV)
+    bb = torch.zeros(c.n + 1, dtype=torch.float64, device=DEV)
+    x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+    with pc.Server(GiB, 2) as srv:
+        ib = srv.submit(bad, bb, xb, 3, lambda_min=c.lo, lambda_max=c.hi)
+        ig = srv.submit(good, b, x, 3, lambda_min=c.lo, lambda_max=c.hi)
+        stb, stg = srv.wait(ib), srv.wait(ig)
+    assert stb["status"] == "INVALID"
+    assert stg["status"] == "OK" and torch.equal(x, _single(pc, good, c, b, 3, "f64", 1)[1])
+
+
+def test_poll_reports_progress(pc):
+    c = case("st7")
+    op = c.operator(torch, DEV)
+    b = _t(W.uniform(51, c.n, -1.0, 1.0))
+    x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+    with pc.Server(GiB, 2) as srv:
+        rid = srv.submit(op, b, x, 5, lambda_min=c.lo, lambda_max=c.hi)
+        import time
+        t0 = time.time()
+        st = None
+        while st is None and time.time() - t0 < 60:
+            st = srv.poll(rid)
+            time.sleep(0.001)
+    assert st is not None and st["status"] == "OK"

@@ -20,6 +20,7 @@ from .grids import (
     rhs_from_solution,
 )
 from .elasticity import q1_reference_stiffness, elasticity_q1_moduli, elasticity_q1_csr
+from .serving import KINDS, serving_trace
 
 __all__ = [
     "splitmix64",
@@ -38,4 +39,6 @@ __all__ = [
     "q1_reference_stiffness",
     "elasticity_q1_moduli",
     "elasticity_q1_csr",
+    "KINDS",
+    "serving_trace",
 ]
