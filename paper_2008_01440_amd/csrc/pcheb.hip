@@ -436,7 +436,18 @@ struct StepTimer {
 
 // ---- fused passes (7-point stencil): S middle steps per launch
 
-template <class T, int S, int TY>
+// Tile shapes of the fused pass: 64 x TY points per block of NT threads.
+#ifndef PCHEB_FUSED_TY
+#define PCHEB_FUSED_TY 32
+#endif
+#ifndef PCHEB_FUSED_NT
+#define PCHEB_FUSED_NT 1024
+#endif
+#ifndef PCHEB_FUSED_V
+#define PCHEB_FUSED_V 3
+#endif
+
+template <class T, int S, int TY, int NT>
 static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T* oa, T* ob, int j,
                          const DevState* guard, hipStream_t s) {
   FusedCoef<typename Store<T>::acc, S> cf;
@@ -449,31 +460,40 @@ static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T*
   const pcheb_operator& op = h.op;
   const uint32_t tiles_x = uint32_t((op.nx + 63) / 64), tiles_y = uint32_t((op.ny + TY - 1) / TY);
   const uint32_t xy = tiles_x * tiles_y;
-  // about 1024 tiles (four per CU), each z range at least 4 S planes deep
+  // about as many tiles as the chip holds blocks at once (256 CUs, 1024 threads
+  // each in flight), each z range at least 4 S planes deep
+  const uint32_t target = 262144u / NT;
   const int max_chunks = std::max(1, op.nz / (4 * S));
-  const int chunks = std::max(1, std::min<int>(max_chunks, int((1024 + xy - 1) / xy)));
+  const int chunks = std::max(1, std::min<int>(max_chunks, int((target + xy - 1) / xy)));
   const int zc = (op.nz + chunks - 1) / chunks;
   const uint32_t ntiles = xy * uint32_t((op.nz + zc - 1) / zc);
-  k_stencil7_fused<S, TY, T><<<dim3(round_grid(ntiles), sl.count), kBlock, 0, s>>>(
-      ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard,
-      h.ldw, sl.first);
+  const dim3 grid(round_grid(ntiles), sl.count);
+  if (PCHEB_FUSED_V == 3 && sizeof(T) < 8)  // the float64 rings do not fit the unrolled form
+    k_stencil7_fused3<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx,
+                                                        op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard, h.ldw,
+                                                        sl.first);
+  else
+    k_stencil7_fused<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx,
+                                                       op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard, h.ldw,
+                                                       sl.first);
 }
 
 template <class T>
 static void launch_fused_any(const Handle& h, Slots sl, int S, const T* ya, const T* yb, T* oa, T* ob, int j,
                              const DevState* guard, hipStream_t s) {
+  constexpr int TY = PCHEB_FUSED_TY, NT = PCHEB_FUSED_NT;
   if constexpr (sizeof(T) == 8) {
     if (S == 2)
-      launch_fused<T, 2, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
     else
-      launch_fused<T, 3, 4>(h, sl, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 3, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
   } else {
     if (S == 2)
-      launch_fused<T, 2, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
     else if (S == 3)
-      launch_fused<T, 3, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 3, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
     else
-      launch_fused<T, 4, 8>(h, sl, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 4, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
   }
 }
 
