@@ -27,12 +27,20 @@
 // l >= 2 is y_{j+l-2}; levels 1..S have registers and LDS planes, level S+1
 // goes straight to memory.
 //
-// k_stencil7_fused3 computes the same values in the same order without
-// branches: LDS planes carry a margin of RX + 1 entries on both sides so every
-// thread may read its four in-plane neighbours, loads use clamped in-grid
-// addresses, and points outside a level's region are masked with selects.  The
-// z loop is unrolled by three, the period of the register rings, so ring slots
-// are fixed per unrolled copy instead of being shifted with moves.
+// k_stencil7_fused_buf (float32 and bfloat16 storage, x-y planes under 2 GiB)
+// computes the same values in the same order with fewer instructions per
+// point:
+//  * memory accesses are buffer instructions: each plane of a vector gets a
+//    descriptor whose range is the plane (empty for planes outside the grid),
+//    and lanes whose point is outside the grid, or whose result is not an
+//    output, use an offset beyond the range, so loads return zero and stores
+//    are dropped without masks or branches;
+//  * the LDS holds one record per region point with the last three planes of
+//    every level (odd stride, so a wavefront's accesses hit distinct banks);
+//    with the z loop unrolled by three, the period of the rings, every LDS
+//    access is an immediate offset from one base per owned point and the
+//    register rings need no moves;
+//  * the neighbour reads of level l+1 are issued while level l computes.
 #pragma once
 
 #include <type_traits>
@@ -183,14 +191,42 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused(const T* __restrict__ ya,
   }
 }
 
+// Raw buffer accesses: descriptor word 3 of the gfx9 family for untyped 32-bit
+// accesses; an offset at or beyond the descriptor's range reads zero and
+// drops stores.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kOutOfRange = 0x7FFFFFF0;
+
+template <class T>
+struct BufIo;
+
+template <>
+struct BufIo<float> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+  }
+};
+
+template <>
+struct BufIo<bf16> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
+    return bf16_to_float(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(float_to_bf16(v), r, off, 0, 0);
+  }
+};
+
 template <int S, int TY, int NT, class T>
-__global__ __launch_bounds__(NT) void k_stencil7_fused3(const T* __restrict__ ya, const T* __restrict__ yb,
-                                                       const T* __restrict__ sv, T* __restrict__ out_a,
-                                                       T* __restrict__ out_b, FusedCoef<typename Store<T>::acc, S> cf,
-                                                       int nx, int ny, int nz, int zc, uint32_t tiles_x,
-                                                       uint32_t tiles_y, uint32_t ntiles, const DevState* guard,
-                                                       int64_t ld, int slot0) {
-  using acc = typename Store<T>::acc;
+__global__ __launch_bounds__(NT) void k_stencil7_fused_buf(const T* __restrict__ ya, const T* __restrict__ yb,
+                                                           const T* __restrict__ sv, T* __restrict__ out_a,
+                                                           T* __restrict__ out_b, FusedCoef<float, S> cf, int nx,
+                                                           int ny, int nz, int zc, uint32_t tiles_x,
+                                                           uint32_t tiles_y, uint32_t ntiles, const DevState* guard,
+                                                           int64_t ld, int slot0) {
   constexpr int TX = 64;
   constexpr int RX = TX + 2 * S;
   constexpr int RY = TY + 2 * S;
@@ -198,7 +234,9 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused3(const T* __restrict__ ya
   constexpr int P = (NP + NT - 1) / NT;  // region points per thread
   constexpr int PAD = RX + 1;            // margin: q - RX - 1 >= 0 and q + RX + 1 < NPL for every q used
   constexpr int NPL = NP + 2 * PAD;
-  __shared__ acc plane_buf[S][2][NPL];
+  constexpr int E = int(sizeof(T));
+  constexpr int R = (3 * S) % 2 == 0 ? 3 * S + 1 : 3 * S;  // LDS record of a point: its S x 3 planes, odd stride
+  __shared__ float lds[NPL * R];
   const int slot = slot0 + int(blockIdx.y);  // solve slot: vectors offset by slot * ld
   if (guard && guard[slot].done != kRunning) return;
   ya += slot * ld;
@@ -208,7 +246,14 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused3(const T* __restrict__ ya
   out_b += slot * ld;
   const int tid = threadIdx.x;
   const int64_t plane = int64_t(nx) * ny;
-  const acc sixth = acc(1.0 / 6.0);
+  const int plane_bytes = int(plane * E);
+  const float sixth = 1.0f / 6.0f;
+  // descriptor of plane zz of a vector (an empty range outside the grid)
+  auto rsrc = [&](const T* base, int zz) {
+    const bool ok = zz >= 0 && zz < nz;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base) + plane * (ok ? zz : 0), 0,
+                                             ok ? plane_bytes : 0, kBufferWord3);
+  };
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
     const int tx = int(t % tiles_x);
@@ -222,124 +267,129 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused3(const T* __restrict__ ya
     const int nadv = (z1 - z0) + 2 * S;
 
     // owned points p = tid + NT m: top[m] is the highest level whose region
-    // contains the point (0 outside the grid or for p >= NP), inner[m] marks
-    // the tile interior, col[m] the in-plane offset (0 when outside), q[m] the
-    // LDS index (lanes without a point use the first entry of the tail margin,
-    // which no point with a valid value reads).
-    int col[P], top[P], q[P];
-    bool inner[P];
+    // contains the point (0 outside the grid or for p >= NP); dom[m] says the
+    // point is in the grid; ldo[m] / sto[m] are the byte offsets of its loads
+    // and output stores in a plane (out of range where there is nothing to
+    // load or store); q[m] is its LDS index (lanes without a point use the
+    // first entry of the tail margin, which no point with a valid value reads).
+    int top[P], q[P], ldo[P], sto[P];
+    bool dom[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
       const int p = tid + NT * m;
       const int ry = p / RX, rx = p - (p / RX) * RX;
       const int gx = x0 + rx, gy = y0 + ry;
-      const bool dom = p < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      dom[m] = p < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
       const int lx = rx + 1 < RX - rx ? rx + 1 : RX - rx;
       const int ly = ry + 1 < RY - ry ? ry + 1 : RY - ry;
-      top[m] = dom ? (lx < ly ? lx : ly) : 0;
-      inner[m] = dom && rx >= S && rx < S + TX && ry >= S && ry < S + TY;
-      col[m] = dom ? gx + nx * gy : 0;
+      top[m] = dom[m] ? (lx < ly ? lx : ly) : 0;
+      const bool inner = dom[m] && rx >= S && rx < S + TX && ry >= S && ry < S + TY;
+      ldo[m] = dom[m] ? (gx + nx * gy) * E : kOutOfRange;
+      sto[m] = inner ? (gx + nx * gy) * E : kOutOfRange;
       q[m] = p < NP ? p + PAD : NP + PAD;
     }
-    acc L[S][3][P];  // ring of the last three planes of level l at [l-1]
-    acc sr[S][P];    // s at the planes of levels 2..S+1 ([0] = level 2's plane)
+    float* rec[P];  // rec[m][(RX + d) * R + k]: slot k of the record of point q + d (d = -RX, -1, 0, 1, RX)
+#pragma unroll
+    for (int m = 0; m < P; ++m) rec[m] = lds + (q[m] - RX) * R;
+    float L[S][3][P];  // ring of the last three planes of level l at [l-1]
+    float sr[S][P];    // s at the planes of levels 2..S+1 ([0] = level 2's plane)
 #pragma unroll
     for (int l = 0; l < S; ++l) {
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        L[l][0][m] = L[l][1][m] = L[l][2][m] = acc(0);
-        sr[l][m] = acc(0);
+        L[l][0][m] = L[l][1][m] = L[l][2][m] = 0.0f;
+        sr[l][m] = 0.0f;
       }
     }
-    // loads of the next step land here unmasked; oka / okb say whether their
-    // planes are in range, dom[m] whether the point is in the grid, and the
-    // zeros are applied when the values are used
-    acc nya[P], ns[P], nyb[P];
-    bool dom[P];
-#pragma unroll
-    for (int m = 0; m < P; ++m) dom[m] = top[m] > 0;
-    bool oka = false, okb = false;
+    float nya[P], ns[P], nyb[P];  // loads of the next step (zero outside the grid)
     auto fetch = [&](int za, int zb) {
-      oka = za >= 0 && za < nz;
-      okb = zb >= 0 && zb < nz;
-      const T* pa = ya + plane * (oka ? za : 0);
-      const T* ps = sv + plane * (okb ? zb : 0);
-      const T* pb = yb + plane * (okb ? zb : 0);
+      const auto ra = rsrc(ya, za), rs = rsrc(sv, zb);
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        nya[m] = Store<T>::ld(pa, col[m]);
-        ns[m] = Store<T>::ld(ps, col[m]);
-        nyb[m] = Store<T>::ld(pb, col[m]);
+        nya[m] = BufIo<T>::ld(ra, ldo[m]);
+        ns[m] = BufIo<T>::ld(rs, ldo[m]);
       }
     };
-    // One step of the pipeline; PH = adv mod 3 fixes the ring slots.  Planes
-    // outside the grid hold zeros in every level (inputs are masked, computed
-    // values outside the grid are set to zero), which supplies the Dirichlet
-    // zeros of the z neighbours without tests.
+    auto fetch_yb = [&](int zb) {  // y_{j-2} is used by level 2 only: loaded once level 2 is done
+      const auto rb = rsrc(yb, zb);
+#pragma unroll
+      for (int m = 0; m < P; ++m) nyb[m] = BufIo<T>::ld(rb, ldo[m]);
+    };
+    // One step of the pipeline; PH = adv mod 3 fixes the register ring slots
+    // and the LDS ring slots.  Level l writes its plane at phase ph into slot
+    // (l - 1) * 3 + (ph - (l - 1)) mod 3 of the point records; level l + 1
+    // reads it at phase ph + 1.  Every LDS access of a thread is an immediate
+    // offset from one base per owned point.
     auto advance = [&](auto phase, int adv) {
       constexpr int PH = decltype(phase)::value;
       constexpr int K0 = PH, K1 = (PH + 2) % 3, K2 = (PH + 1) % 3;  // newest, one below, two below
-      acc cya[P], ybc[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        cya[m] = (oka && dom[m]) ? nya[m] : acc(0);
+        L[0][K0][m] = nya[m];
 #pragma unroll
         for (int l = S - 1; l > 0; --l) sr[l][m] = sr[l - 1][m];
-        sr[0][m] = (okb && dom[m]) ? ns[m] : acc(0);
-        ybc[m] = (okb && dom[m]) ? nyb[m] : acc(0);
+        sr[0][m] = ns[m];
       }
       if (adv + 1 < nadv) fetch(zs + adv + 1, zs + adv);
-      // In-plane neighbour sums: every level reads a plane written in the
-      // previous step, so the sums of level l + 1 are read while level l computes.
-      acc nbs[2][P];
-      auto read_sums = [&](int l, acc* out) {
-        const acc* nb_plane = plane_buf[l - 2][(zs + adv - (l - 1)) & 1];
+      float nbs[2][P];
+      auto read_sums = [&](auto level, float* out) {
+        constexpr int l = decltype(level)::value;
+        constexpr int k = (l - 2) * 3 + ((PH - l + 1) % 3 + 3) % 3;  // level l-1, slot written last step
 #pragma unroll
-        for (int m = 0; m < P; ++m) {
-          const int qm = q[m];
-          out[m] = (nb_plane[qm - 1] + nb_plane[qm + 1]) + (nb_plane[qm - RX] + nb_plane[qm + RX]);
-        }
+        for (int m = 0; m < P; ++m)
+          out[m] = (rec[m][(RX - 1) * R + k] + rec[m][(RX + 1) * R + k]) + (rec[m][k] + rec[m][2 * RX * R + k]);
       };
-      read_sums(2, nbs[0]);
-      const int zin1 = zs + adv;  // level 1: the input plane
+      read_sums(std::integral_constant<int, 2>{}, nbs[0]);
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        L[0][K0][m] = cya[m];
-        plane_buf[0][zin1 & 1][q[m]] = cya[m];
-      }
-#pragma unroll
-      for (int l = 2; l <= S + 1; ++l) {
+      for (int m = 0; m < P; ++m) rec[m][RX * R + PH] = L[0][K0][m];  // level 1: the input plane
+      auto level = [&](auto lv) {
+        constexpr int l = decltype(lv)::value;
+        constexpr int li = l <= S ? l - 1 : 0;
+        constexpr int lp = l >= 3 ? l - 3 : 0;
         const int z = zs + adv - (l - 1);
         const bool zin = z >= 0 && z < nz;
-        const bool out_plane = z >= z0 && z < z1;
-        const acc a = cf.a[l - 2], b = cf.b[l - 2], c = cf.c[l - 2];
-        const int li = l <= S ? l - 1 : 0;
-        const int lp = l >= 3 ? l - 3 : 0;
-        T* out_z = (l == S ? out_b : out_a) + plane * (zin ? z : 0);
-        if (l + 1 <= S + 1) read_sums(l + 1, nbs[(l - 1) & 1]);
-        acc v[P];
+        const float a = cf.a[l - 2], b = cf.b[l - 2], c = cf.c[l - 2];
+        if constexpr (l + 1 <= S + 1) read_sums(std::integral_constant<int, l + 1>{}, nbs[(l - 1) & 1]);
+        float v[P];
+        if (zin) {
 #pragma unroll
-        for (int m = 0; m < P; ++m) {
-          const acc yc = L[l - 2][K1][m];
-          acc nb = nbs[l & 1][m];
-          nb += L[l - 2][K0][m] + L[l - 2][K2][m];
-          const acc yprev = (l == 2) ? ybc[m] : L[lp][K2][m];
-          acc w = a * yc + c * (sr[l - 2][m] - (yc - nb * sixth));  // same order as EpiChebStep
-          w -= b * yprev;
-          v[m] = (zin && l <= top[m]) ? w : acc(0);
-          if (l >= S && zin && out_plane && inner[m]) Store<T>::st(out_z, col[m], v[m]);
+          for (int m = 0; m < P; ++m) {
+            const float yc = L[l - 2][K1][m];
+            float nb = nbs[l & 1][m];
+            nb += L[l - 2][K0][m] + L[l - 2][K2][m];
+            const float yprev = (l == 2) ? nyb[m] : L[lp][K2][m];
+            float w = a * yc + c * (sr[l - 2][m] - (yc - nb * sixth));  // same order as EpiChebStep
+            w -= b * yprev;
+            v[m] = dom[m] ? w : 0.0f;
+          }
+          if (l >= S && z >= z0 && z < z1) {
+            const auto ro = rsrc(l == S ? out_b : out_a, z);
+#pragma unroll
+            for (int m = 0; m < P; ++m) BufIo<T>::st(ro, sto[m], v[m]);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < P; ++m) v[m] = 0.0f;
         }
-        if (l <= S) {
+        if constexpr (l <= S) {
+          constexpr int k = li * 3 + ((PH - (l - 1)) % 3 + 3) % 3;
 #pragma unroll
           for (int m = 0; m < P; ++m) {
             L[li][K0][m] = v[m];
-            plane_buf[li][z & 1][q[m]] = v[m];
+            rec[m][RX * R + k] = v[m];
           }
         }
-      }
+      };
+      level(std::integral_constant<int, 2>{});
+      if (adv + 1 < nadv) fetch_yb(zs + adv);
+      level(std::integral_constant<int, 3>{});
+      if constexpr (S >= 3) level(std::integral_constant<int, 4>{});
+      if constexpr (S >= 4) level(std::integral_constant<int, 5>{});
+      if constexpr (S >= 5) level(std::integral_constant<int, 6>{});
       __syncthreads();
     };
     fetch(zs, zs - 1);
+    fetch_yb(zs - 1);
     for (int adv = 0; adv < nadv; adv += 3) {
       advance(std::integral_constant<int, 0>{}, adv);
       if (adv + 1 < nadv) advance(std::integral_constant<int, 1>{}, adv + 1);

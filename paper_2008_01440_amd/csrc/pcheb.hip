@@ -443,9 +443,6 @@ struct StepTimer {
 #ifndef PCHEB_FUSED_NT
 #define PCHEB_FUSED_NT 1024
 #endif
-#ifndef PCHEB_FUSED_V
-#define PCHEB_FUSED_V 3
-#endif
 
 template <class T, int S, int TY, int NT>
 static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T* oa, T* ob, int j,
@@ -468,14 +465,18 @@ static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T*
   const int zc = (op.nz + chunks - 1) / chunks;
   const uint32_t ntiles = xy * uint32_t((op.nz + zc - 1) / zc);
   const dim3 grid(round_grid(ntiles), sl.count);
-  if (PCHEB_FUSED_V == 3 && sizeof(T) < 8)  // the float64 rings do not fit the unrolled form
-    k_stencil7_fused3<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx,
-                                                        op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard, h.ldw,
-                                                        sl.first);
-  else
-    k_stencil7_fused<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, reinterpret_cast<const T*>(h.s), oa, ob, cf, op.nx,
-                                                       op.ny, op.nz, zc, tiles_x, tiles_y, ntiles, guard, h.ldw,
-                                                       sl.first);
+  const T* sv = reinterpret_cast<const T*>(h.s);
+  if constexpr (sizeof(T) < 8) {
+    // buffer-addressed form: plane byte offsets must fit the 32-bit range
+    if (int64_t(op.nx) * op.ny * int64_t(sizeof(T)) <= 0x7FFFFFF0) {
+      k_stencil7_fused_buf<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc,
+                                                             tiles_x, tiles_y, ntiles, guard, h.ldw, sl.first);
+      return;
+    }
+  }
+  // float64 (its rings do not fit the unrolled form in 128 registers) and larger planes
+  k_stencil7_fused<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
+                                                     tiles_y, ntiles, guard, h.ldw, sl.first);
 }
 
 template <class T>
