@@ -305,6 +305,7 @@ def run_serve(args, rate, torch, pc, W, dev):
     srv = pc.Server(int(args.serve_budget_gib * (1 << 30)), args.serve_nrhs)
     outstanding = {}  # id -> (request index, b, x)
     lat, iters, status = [], [], {}
+    failures = []
     rejected = 0
     start = time.perf_counter()
     i = 0
@@ -334,6 +335,10 @@ def run_serve(args, rate, torch, pc, W, dev):
             lat.append(time.perf_counter() - start - tr["t"][j])
             iters.append(st["iters"])
             status[st["status"]] = status.get(st["status"], 0) + 1
+            if st["status"] != "OK" and len(failures) < 12:
+                failures.append({"request": int(j), "op": W.KINDS[int(tr["kind"][j])], "N": int(tr["N"][j]),
+                                 "status": st["status"], "iters": st["iters"], "relres": st["relres"],
+                                 "error": st.get("error", "")})
             if j in want_check:
                 check[j] = (b, x, st)
         if i < nreq and not outstanding:
@@ -373,6 +378,7 @@ def run_serve(args, rate, torch, pc, W, dev):
         "groups_created": sv["groups_created"], "groups_evicted": sv["groups_evicted"],
         "launches": sv["launches"], "batch_hist": sv["batch_hist"],
         "invariance": f"{same}/{len(check)} bitwise equal to solo solves",
+        "failures": failures,
         "data": "synthetic", "n_gpus": 1,
     }
     print(json.dumps(out), flush=True)

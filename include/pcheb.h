@@ -279,8 +279,9 @@ pcheb_status pserve_create(size_t hbm_budget, int32_t max_nrhs, pserve_handle* o
 pcheb_status pserve_submit(pserve_handle srv, const pserve_request* req, uint64_t* id);
 
 /* *done = 1 and stats filled once the request has finished (stats->seconds is
- * the latency from submission to completion), else *done = 0.  NOT_FOUND for
- * unknown ids. */
+ * the latency from submission to completion; stats->status its final status,
+ * with the reason in pcheb_last_error() when it is not OK), else *done = 0.
+ * NOT_FOUND for unknown ids. */
 pcheb_status pserve_poll(pserve_handle srv, uint64_t id, int32_t* done, pcg_stats* stats);
 
 /* Block until the request has finished; returns its solve status (OK,

@@ -368,7 +368,10 @@ class Server:
         if not done.value:
             return None
         self._keep.pop(rid, None)
-        return _stats_dict(st, st.status)
+        out = _stats_dict(st, st.status)
+        if st.status != 0:
+            out["error"] = pcheb_last_error()
+        return out
 
     def wait(self, rid: int, check: bool = False) -> dict:
         """Block until the request finishes; the dict's 'status' is its final status."""

@@ -758,7 +758,7 @@ static void setup_preconditioner(Handle& h, hipStream_t s) {
 }
 
 // Solve workspace for `cap` slots (reallocated when a call needs more).
-void ensure_workspace(Handle& h, int cap) {
+void ensure_workspace(Handle& h, int cap, hipStream_t stream) {
   if (cap <= h.cap) return;
   release_workspace(h);
   const size_t lw = size_t(h.ldw) * size_t(cap);
@@ -773,7 +773,9 @@ void ensure_workspace(Handle& h, int cap) {
   h.z = static_cast<double*>(alloc_into(ws, lw * 8));
   h.st = static_cast<DevState*>(alloc_into(ws, size_t(cap) * sizeof(DevState)));
   h.partials = static_cast<double*>(alloc_into(ws, size_t(cap) * kMaxGrid * kMaxReduce * sizeof(double)));
-  PCHEB_HIP_CHECK(hipMemset(h.st, 0, size_t(cap) * sizeof(DevState)));
+  // on the stream the states are used on next (a non-blocking stream is not
+  // ordered after the legacy default stream)
+  PCHEB_HIP_CHECK(hipMemsetAsync(h.st, 0, size_t(cap) * sizeof(DevState), stream));
   PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&h.st_host), 2 * size_t(cap) * sizeof(DevState),
                                 hipHostMallocDefault));
   std::memset(h.st_host, 0, 2 * size_t(cap) * sizeof(DevState));
@@ -888,7 +890,10 @@ static void capture_pair(Handle& h, Slots sl, double* x, int64_t ldx, int flexib
   if (!h.capture_stream) PCHEB_HIP_CHECK(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking));
   hipStream_t s = h.capture_stream;
   hipGraph_t graph = nullptr;
-  PCHEB_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  // Relaxed: the capture holds kernel launches on a private stream only, and
+  // other threads (a server's set-up and worker threads, the caller's) may
+  // allocate or synchronise meanwhile without invalidating it.
+  PCHEB_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
   try {
     enqueue_iteration<T>(h, sl, x, ldx, nullptr, 0, 0, flexible, false, nullptr, s);
     enqueue_iteration<T>(h, sl, x, ldx, nullptr, 0, 1, flexible, false, nullptr, s);
@@ -948,6 +953,17 @@ void solver_iteration_pairs(Handle& h, Slots sl, double* x, int64_t ldx, int pai
   PCHEB_HIP_CHECK(hipGetLastError());
 }
 
+template <class T>
+static void prepare_graph(Handle& h, Slots sl, double* x, int64_t ldx, int flexible) {
+  if (h.graph_exec == nullptr || h.graph_x != x || h.graph_ldx != ldx ||
+      h.graph_slots != sl.first * 65536 + sl.count || h.graph_flags != uint32_t(flexible))
+    capture_pair<T>(h, sl, x, ldx, flexible);
+}
+
+void solver_prepare_graph(Handle& h, Slots sl, double* x, int64_t ldx, int flexible) {
+  PCHEB_BY_PREC(h, prepare_graph, h, sl, x, ldx, flexible);
+}
+
 void solver_finish(Handle& h, Slots sl, const double* b, int64_t ldb, const double* x, int64_t ldx, hipStream_t s) {
   PCHEB_BY_PREC(h, enqueue_finish, h, sl, b, ldb, x, ldx, s);
   PCHEB_HIP_CHECK(hipGetLastError());
@@ -980,7 +996,7 @@ template <class T>
 static pcheb_status solve_impl(Handle& h, const double* b, double* x, int nrhs, int64_t ld, double tol, int maxit,
                                uint32_t flags, pcg_stats* stats, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  ensure_workspace(h, nrhs);
+  ensure_workspace(h, nrhs, s);
   const Slots sl{0, nrhs};
   const int flexible = (flags & PCG_FLEXIBLE) ? 1 : 0;
   const bool timed = (flags & PCG_TIME_KERNELS) != 0;
@@ -1110,7 +1126,7 @@ Handle* create_handle(const pcheb_operator* A, const pcheb_params* p, hipStream_
   try {
     setup_operator(*h, stream);
     setup_preconditioner(*h, stream);
-    ensure_workspace(*h, 1);
+    ensure_workspace(*h, 1, stream);
   } catch (...) {
     release(*h);
     delete h;

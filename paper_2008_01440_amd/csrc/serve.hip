@@ -2,10 +2,12 @@
 //
 // Requests that share an operator and parameters form a group: one resident
 // handle (operator data, bounds, workspace for `cap` right-hand sides), one
-// stream, and a slot table.  A worker thread loops over
+// stream, and a slot table.  A set-up thread builds groups (allocation and the
+// bound estimate) while a worker thread loops over
 //   * cancellations and completions (non-blocking event queries),
-//   * admission of queued requests into free slots, creating groups while the
-//     device-memory budget allows and evicting idle groups least recently used,
+//   * admission of queued requests into free slots; a request without a group
+//     reserves the group's memory (evicting idle groups, least recently used,
+//     when the budget requires) and queues its set-up,
 //   * one launch of a pair of PCG iterations per group with work in flight,
 //     replayed from the handle's HIP graph over all of the group's slots.
 // A slot's scalars and stop flag live on the device; a slot joins between
@@ -107,12 +109,27 @@ struct Group {
   }
 };
 
+// Set-up of a group (operator data, bound estimate, workspace), done by the
+// set-up thread while the worker keeps the running groups going.
+struct SetupJob {
+  GroupKey key;
+  pserve_request req;
+  size_t bytes = 0;  // reserved against the budget when the job was queued
+  std::unique_ptr<Group> group;
+  pcheb_status status = PCHEB_OK;
+  std::string msg;
+  bool done = false;
+};
+
 struct Server {
   size_t budget = 0;
   int max_nrhs = 1;
   int device = 0;
   std::mutex mu;
-  std::condition_variable cv_done, cv_work;
+  std::condition_variable cv_done, cv_work, cv_setup;
+  std::deque<std::shared_ptr<SetupJob>> setup_q;  // waiting for the set-up thread
+  std::vector<std::shared_ptr<SetupJob>> setups;  // queued, running or finished, not yet collected
+  std::thread setup_thread;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> reqs;
   std::deque<uint64_t> queue;
   std::vector<std::unique_ptr<Group>> groups;
@@ -183,7 +200,7 @@ static std::unique_ptr<Group> create_group(Server& sv, const pserve_request& r) 
     }
     const pcheb_params p = params_of(r, lmin, lmax);
     g->h = create_handle(&r.op, &p, g->stream);
-    ensure_workspace(*g->h, g->cap);
+    ensure_workspace(*g->h, g->cap, g->stream);
     const size_t lw = size_t(g->h->ldw) * size_t(g->cap);
     PCHEB_HIP_CHECK(hipMalloc(&g->X, lw * sizeof(double)));
     PCHEB_HIP_CHECK(hipMalloc(&g->B, lw * sizeof(double)));
@@ -201,6 +218,7 @@ static std::unique_ptr<Group> create_group(Server& sv, const pserve_request& r) 
     solver_init_states(*g->h, all, 1e-8, 1, 1, g->stream);
     solver_retire(*g->h, all, g->stream);
     PCHEB_HIP_CHECK(hipStreamSynchronize(g->stream));
+    solver_prepare_graph(*g->h, all, g->X, g->h->ldw, 1);
     g->bytes = request_bytes(r, g->cap);
     g->last_used = Clock::now();
   } catch (...) {
@@ -239,6 +257,37 @@ static bool worker_step(Server& sv) {
     rq.stats.status = PCHEB_NOT_CONVERGED;
     finish_request(sv, rq, PCHEB_NOT_CONVERGED);
     progress = true;
+  }
+
+  // groups whose set-up finished: add them, or fail the requests waiting for them
+  for (auto it = sv.setups.begin(); it != sv.setups.end();) {
+    SetupJob& job = **it;
+    if (!job.done) {
+      ++it;
+      continue;
+    }
+    progress = true;
+    if (job.group) {
+      size_t at = sv.groups.size();
+      for (size_t gi = 0; gi < sv.groups.size(); ++gi)
+        if (!sv.groups[gi]) at = gi;
+      if (at == sv.groups.size()) sv.groups.emplace_back();
+      sv.groups[at] = std::move(job.group);
+      sv.st.groups_created += 1;
+    } else {
+      sv.used -= job.bytes;
+      const std::vector<uint64_t> waiting(sv.queue.begin(), sv.queue.end());
+      for (const uint64_t id : waiting) {
+        Request& rq = *sv.reqs.at(id);
+        if (rq.cancel || !(key_of(rq.req) == job.key)) continue;
+        rq.stats.status = job.status;
+        rq.error = job.msg;
+        sv.st.rejected += 1;
+        sv.queue.erase(std::find(sv.queue.begin(), sv.queue.end(), id));
+        finish_request(sv, rq, job.status);
+      }
+    }
+    it = sv.setups.erase(it);
   }
 
   for (size_t gi = 0; gi < sv.groups.size(); ++gi) {
@@ -294,7 +343,9 @@ static bool worker_step(Server& sv) {
     for (size_t gi = 0; gi < sv.groups.size(); ++gi)
       if (sv.groups[gi] && sv.groups[gi]->key == key) gidx = int(gi);
     if (gidx < 0) {
-      if (!may_create) continue;
+      bool pending = false;
+      for (const auto& job : sv.setups) pending = pending || job->key == key;
+      if (pending || !may_create) continue;  // its group is being set up, or memory is short
       const size_t need = request_bytes(rq.req, sv.max_nrhs);
       while (sv.used + need > sv.budget) {  // evict the least recently used idle group
         int victim = -1;
@@ -313,39 +364,17 @@ static bool worker_step(Server& sv) {
         may_create = false;
         continue;
       }
-      std::unique_ptr<Group> g;
-      pcheb_status err = PCHEB_OK;
-      std::string msg;
-      lk.unlock();  // set-up may take a while (bound estimate); calls from other threads proceed
-      try {
-        g = create_group(sv, rq.req);
-      } catch (const Error& e) {
-        err = e.status;
-        msg = e.msg;
-      } catch (const std::bad_alloc&) {
-        err = PCHEB_OOM;
-        msg = "host allocation failed";
-      }
-      lk.lock();
-      progress = true;
-      if (!g) {
-        rq.stats.status = err;
-        rq.error = msg;
-        sv.st.rejected += 1;
-        dequeue(id);
-        finish_request(sv, rq, err);
-        continue;
-      }
-      size_t at = sv.groups.size();
-      for (size_t gi = 0; gi < sv.groups.size(); ++gi)
-        if (!sv.groups[gi]) at = gi;
-      if (at == sv.groups.size()) sv.groups.emplace_back();
-      sv.used += g->bytes;
+      auto job = std::make_shared<SetupJob>();
+      job->key = key;
+      job->req = rq.req;
+      job->bytes = need;
+      sv.used += need;  // reserved now, so later admissions see it
       sv.st.bytes_high_water = std::max<int64_t>(sv.st.bytes_high_water, int64_t(sv.used));
-      sv.st.groups_created += 1;
-      sv.groups[at] = std::move(g);
-      gidx = int(at);
-      if (rq.cancel) continue;  // cancelled while the group was being built
+      sv.setups.push_back(job);
+      sv.setup_q.push_back(job);
+      sv.cv_setup.notify_one();
+      progress = true;
+      continue;  // admitted once the group exists
     }
     Group& g = *sv.groups[size_t(gidx)];
     int slot = -1;
@@ -430,8 +459,44 @@ static void worker_main(Server* sv) {
           destroy_group(*g);
           g.reset();
         }
-      sv->used = 0;
+      sv->used = 0;  // what remains reserved: set-ups not collected yet
+      for (const auto& job : sv->setups) sv->used += job->bytes;
     }
+  }
+}
+
+static void setup_main(Server* sv) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    std::shared_ptr<SetupJob> job;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_setup.wait(lk, [&] { return sv->stop || !sv->setup_q.empty(); });
+      if (sv->stop) break;
+      job = sv->setup_q.front();
+      sv->setup_q.pop_front();
+    }
+    std::unique_ptr<Group> g;
+    pcheb_status status = PCHEB_OK;
+    std::string msg;
+    try {
+      g = create_group(*sv, job->req);
+    } catch (const Error& e) {
+      status = e.status;
+      msg = e.msg;
+    } catch (const std::bad_alloc&) {
+      status = PCHEB_OOM;
+      msg = "host allocation failed";
+    } catch (...) {
+      status = PCHEB_HIP;
+      msg = "unexpected internal error";
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    job->group = std::move(g);
+    job->status = status;
+    job->msg = msg;
+    job->done = true;
+    sv->cv_work.notify_one();
   }
 }
 
@@ -474,6 +539,7 @@ pcheb_status pserve_create(size_t hbm_budget, int32_t max_nrhs, pserve_handle* o
     sv->st.budget = int64_t(hbm_budget);
     PCHEB_HIP_CHECK(hipGetDevice(&sv->device));
     sv->worker = std::thread(worker_main, sv);
+    sv->setup_thread = std::thread(setup_main, sv);
     *out = reinterpret_cast<pserve_handle>(sv);
     return PCHEB_OK;
   });
@@ -514,7 +580,10 @@ pcheb_status pserve_poll(pserve_handle s, uint64_t id, int32_t* done, pcg_stats*
     if (it == sv->reqs.end()) fail(PCHEB_NOT_FOUND, "unknown request id");
     *done = it->second->state == RState::Done ? 1 : 0;
     if (*done) {
-      if (stats) *stats = it->second->stats;
+      const Request& rq = *it->second;
+      if (stats) *stats = rq.stats;
+      if (rq.result != PCHEB_OK)
+        set_last_error(rq.cancel ? "request cancelled" : !rq.error.empty() ? rq.error : "request did not converge");
       sv->reqs.erase(it);  // reported: the id is released
     }
     return PCHEB_OK;
@@ -579,10 +648,14 @@ pcheb_status pserve_destroy(pserve_handle s) {
       std::lock_guard<std::mutex> lk(sv->mu);
       sv->stop = true;
       sv->cv_work.notify_all();
+      sv->cv_setup.notify_all();
     }
     if (sv->worker.joinable()) sv->worker.join();
+    if (sv->setup_thread.joinable()) sv->setup_thread.join();
     for (auto& g : sv->groups)
       if (g) destroy_group(*g);
+    for (auto& job : sv->setups)
+      if (job->group) destroy_group(*job->group);
     {
       std::lock_guard<std::mutex> lk(sv->mu);
       for (auto& kv : sv->reqs)

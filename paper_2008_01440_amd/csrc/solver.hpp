@@ -13,8 +13,9 @@ void destroy_handle(Handle* h);
 size_t footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs);
 const char* last_error_cstr();
 
-// Workspace for at least `cap` slots (frees and reallocates the workspace).
-void ensure_workspace(Handle& h, int cap);
+// Workspace for at least `cap` slots (frees and reallocates the workspace);
+// the slot states are cleared on `stream`.
+void ensure_workspace(Handle& h, int cap, hipStream_t stream);
 
 // Fresh scalars for the slots (tolerance, iteration limit, flexible beta).
 void solver_init_states(Handle& h, Slots sl, double tol, int maxit, int flexible, hipStream_t s);
@@ -23,6 +24,9 @@ void solver_retire(Handle& h, Slots sl, hipStream_t s);
 // r = b - A x (or x = 0, r = b), the first preconditioner application and gamma.
 void solver_start(Handle& h, Slots sl, const double* b, int64_t ldb, double* x, int64_t ldx, bool x0_given,
                   int flexible, hipStream_t s);
+// Capture the graph of two PCG iterations of the slots now (otherwise the first
+// solver_iteration_pairs call with these arguments does).
+void solver_prepare_graph(Handle& h, Slots sl, double* x, int64_t ldx, int flexible);
 // `pairs` x two PCG iterations of the slots, replayed from a HIP graph.
 void solver_iteration_pairs(Handle& h, Slots sl, double* x, int64_t ldx, int pairs, int flexible, hipStream_t s);
 // True residual of the slots (norms into their scalars).

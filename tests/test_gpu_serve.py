@@ -217,3 +217,38 @@ def test_poll_reports_progress(pc):
             st = srv.poll(rid)
             time.sleep(0.001)
     assert st is not None and st["status"] == "OK"
+
+
+def test_many_new_groups_while_busy(pc):
+    """Groups set up while other groups iterate (the set-up clears slot states on the
+    group's own stream, ordered before the slots start): every request converges and
+    equals its solo solve."""
+    big = pc.Operator.stencil7(96)
+    lo_b, hi_b = W.stencil7_bounds(96)
+    bb = torch.empty(96 ** 3, dtype=torch.float64, device=DEV)
+    pc.pcheb_fill_uniform(bb, 900, -1.0, 1.0)
+    xb = torch.empty_like(bb)
+    sizes = list(range(20, 44))
+    ops = [pc.Operator.stencil7(N) for N in sizes]
+    bs, xs = [], []
+    for j, N in enumerate(sizes):
+        b = torch.empty(N ** 3, dtype=torch.float64, device=DEV)
+        pc.pcheb_fill_uniform(b, 1000 + j, -1.0, 1.0)
+        bs.append(b)
+        xs.append(torch.empty_like(b))
+    with pc.Server(8 * GiB, 2) as srv:
+        ib = srv.submit(big, bb, xb, 30, prec="f32", lambda_min=lo_b, lambda_max=hi_b, fuse_steps=2)
+        ids = []
+        for N, op, b, x in zip(sizes, ops, bs, xs):
+            lo, hi = W.stencil7_bounds(N)
+            ids.append(srv.submit(op, b, x, 30, prec="f32", lambda_min=lo, lambda_max=hi, fuse_steps=2))
+        sts = [srv.wait(i) for i in ids]
+        stb = srv.wait(ib)
+    assert stb["status"] == "OK"
+    for N, op, b, x, st in zip(sizes, ops, bs, xs, sts):
+        assert st["status"] == "OK", (N, st)
+        lo, hi = W.stencil7_bounds(N)
+        with pc.pcheb_setup(op, 30, lo, hi, 1.001, "f32", fuse_steps=2) as h:
+            x1 = torch.zeros_like(b)
+            st1 = pc.pcg_solve(h, b, x1, tol=1e-8, flexible=True)
+        assert st1["iters"] == st["iters"] and torch.equal(x, x1), N
