@@ -193,13 +193,16 @@ const char* pcheb_last_error(void);
 size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs);
 
 /*
- * Extreme Ritz values of nsteps Lanczos steps (full reorthogonalisation) on
- * the Jacobi-scaled operator D^-1/2 A_hat D^-1/2, started from v0 (device
- * float64[n], need not be normalised).  The paper estimates the bounds by
- * the power method and DACG (Sec. 5.1); callers widen lambda_max by a
- * safety factor before pcheb_setup.  Writes *lambda_min, *lambda_max (host).
- * Allocates nsteps + 1 vectors of workspace for the duration of the call.
- * Errors: INVALID, NOT_SPD, OOM, HIP.
+ * Extreme Ritz values of nsteps Lanczos steps (classical Gram-Schmidt
+ * against all previous vectors, twice) on the Jacobi-scaled operator
+ * D^-1/2 A_hat D^-1/2, started from v0 (device float64[n], 16-byte aligned,
+ * need not be normalised).  The tridiagonal stops at the first beta_j that
+ * vanishes relative to alpha_j (exhausted Krylov space).  The paper
+ * estimates the bounds by the power method and DACG (Sec. 5.1); callers
+ * widen lambda_max by a safety factor before pcheb_setup.  Writes
+ * *lambda_min, *lambda_max (host); synchronises `stream` before returning.
+ * Allocates nsteps + 4 vectors of workspace for the duration of the call.
+ * Errors: INVALID (also a zero or non-finite v0), NOT_SPD, OOM, HIP.
  */
 pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
                                    double* lambda_min, double* lambda_max, hipStream_t stream);

@@ -3,6 +3,17 @@
 // few power iterations and DACG (Sec. 5.1); Lanczos gives both ends from one
 // Krylov space.  The Ritz values lie inside the spectrum, so callers widen the
 // upper bound before building the preconditioner.
+//
+// Step j: w = A v_j; alpha_j = (v_j, w); classical Gram-Schmidt against
+// v_0..v_j twice (c = V^T w, w -= V c); beta_j = ||w||; v_{j+1} = w / beta_j.
+// Everything stays on the device: the dot products of a pass are one kernel
+// over w and the basis (up to kCols columns at a time), the first update is
+// fused with the second pass's dot products and the second update with the
+// norm, and one-block finalize kernels sum the partials in block order into
+// the coefficients, alpha, beta and 1/beta that the next kernel reads.  The
+// host reads alpha and beta once at the end and stops the tridiagonal at the
+// first beta that vanishes relative to alpha (the later steps then worked on
+// a meaningless vector and are discarded).
 
 #include <hip/hip_runtime.h>
 
@@ -15,27 +26,116 @@
 
 namespace pcheb {
 
-constexpr int kDotGrid = 512;
+constexpr int kLzGrid = 2048;  // blocks of the vector kernels (partials per column)
+constexpr int kCols = 32;      // basis columns whose dot products one pass accumulates
 
-// partial[b] = sum over this block's share of a[i] * b[i]
-__global__ void k_dot_partial(const double* a, const double* b, int64_t n, double* partial) {
-  double v[1] = {0.0};
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    v[0] += a[i] * b[i];
-  block_sum<1>(v, threadIdx.x);
-  if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
-}
+// Vectors are walked two elements at a time (16-byte accesses; columns of V
+// start at even offsets); element pair q covers 2q and 2q + 1 < n.
 
-// w -= sum_m c[m] V[m]   (V holds m vectors of length n, stride n)
-__global__ void k_sub_combination(double* w, const double* V, const double* c, int m, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += c[j] * V[int64_t(j) * n + i];
-    w[i] -= acc;
+// partial[k * kLzGrid + b] = block b's share of (V[col0 + k], w), k < ncol.
+__global__ __launch_bounds__(kBlock) void k_lz_dots(const double* __restrict__ V, int64_t ldv, int col0, int ncol,
+                                                    const double* __restrict__ w, int64_t n,
+                                                    double* __restrict__ partial) {
+  double acc[kCols];
+#pragma unroll
+  for (int k = 0; k < kCols; ++k) acc[k] = 0.0;
+  const int64_t npairs = n / 2;
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < npairs; q += int64_t(gridDim.x) * blockDim.x) {
+    const double2 wq = ld2(w, 2 * q);
+#pragma unroll
+    for (int k = 0; k < kCols; ++k)
+      if (k < ncol) {
+        const double2 vq = ld2(V + int64_t(col0 + k) * ldv, 2 * q);
+        acc[k] += vq.x * wq.x + vq.y * wq.y;
+      }
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd tail
+    const double wi = w[n - 1];
+#pragma unroll
+    for (int k = 0; k < kCols; ++k)
+      if (k < ncol) acc[k] += V[int64_t(col0 + k) * ldv + n - 1] * wi;
+  }
+  block_sum<kCols>(acc, threadIdx.x);  // all columns at once (fixed order)
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kCols; ++k)
+      if (k < ncol) partial[k * kLzGrid + blockIdx.x] = acc[k];
   }
 }
 
-__global__ void k_scale_copy(const double* a, double* b, double s, int64_t n) {
+// w -= sum_{k < m} c[k] V[k]; then, if DOTS, partials of (V[k], w) for k < m
+// (m <= kCols), and if NORM, partials of (w, w) in column 0.
+template <bool DOTS, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_lz_update(const double* __restrict__ V, int64_t ldv, int m,
+                                                      const double* __restrict__ c, double* __restrict__ w, int64_t n,
+                                                      double* __restrict__ partial) {
+  constexpr int NV = DOTS ? kCols : 1;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  auto one = [&](int64_t i0, int cnt) {  // elements i0 .. i0 + cnt - 1 (cnt = 2, or 1 for the odd tail)
+    double w0 = w[i0], w1 = cnt > 1 ? w[i0 + 1] : 0.0;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double* vk = V + int64_t(k) * ldv + i0;
+      s0 += c[k] * vk[0];
+      if (cnt > 1) s1 += c[k] * vk[1];
+    }
+    w0 -= s0;
+    w1 -= s1;
+    w[i0] = w0;
+    if (cnt > 1) w[i0 + 1] = w1;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int k = 0; k < kCols; ++k)
+        if (k < m) {
+          const double* vk = V + int64_t(k) * ldv + i0;
+          acc[k] += vk[0] * w0 + (cnt > 1 ? vk[1] * w1 : 0.0);
+        }
+    }
+    if constexpr (NORM) acc[0] += w0 * w0 + w1 * w1;
+  };
+  const int64_t npairs = n / 2;
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < npairs; q += int64_t(gridDim.x) * blockDim.x)
+    one(2 * q, 2);
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) one(n - 1, 1);
+  if constexpr (DOTS || NORM) {
+    const int nc = DOTS ? m : 1;
+    block_sum<NV>(acc, threadIdx.x);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (k < nc) partial[k * kLzGrid + blockIdx.x] = acc[k];
+    }
+  }
+}
+
+// One block: out[col0 + k] = sum over blocks of partial[k][.] (each thread a
+// strided share in block order, then the fixed block tree), k < ncol.  With
+// `alpha`, the sum of column j (the step) is also stored in alpha[j].  With
+// `norm`, column 0 is a squared norm: *norm = its square root and *inv = 1 / *norm.
+__global__ __launch_bounds__(kBlock) void k_lz_finalize(const double* __restrict__ partial, int ncol, double* out,
+                                                        int col0, double* alpha, int j, double* norm,
+                                                        double* inv) {
+  for (int k = 0; k < ncol; ++k) {
+    double t[1] = {0.0};
+    for (int b = threadIdx.x; b < kLzGrid; b += blockDim.x) t[0] += partial[k * kLzGrid + b];
+    block_sum<1>(t, threadIdx.x);
+    if (threadIdx.x == 0) {
+      if (out) out[col0 + k] = t[0];
+      if (alpha && col0 + k == j) alpha[j] = t[0];
+      if (norm && k == 0) {
+        const double r = sqrt(t[0]);
+        norm[0] = r;
+        inv[0] = 1.0 / r;
+      }
+    }
+  }
+}
+
+__global__ void k_lz_scale(const double* __restrict__ a, double* __restrict__ b, const double* __restrict__ f,
+                           int64_t n) {
+  const double s = f[0];
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     b[i] = a[i] * s;
 }
@@ -43,19 +143,6 @@ __global__ void k_scale_copy(const double* a, double* b, double s, int64_t n) {
 __global__ void k_isqrt_diag(const double* invd, double c, double* isd, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     isd[i] = sqrt(invd ? invd[i] : c);
-}
-
-// Dot products of w with the first m columns of V, summed on the host in block order.
-static void dots(const double* V, int m, const double* w, int64_t n, double* partial, std::vector<double>& host,
-                 std::vector<double>& out, hipStream_t s) {
-  for (int j = 0; j < m; ++j) k_dot_partial<<<kDotGrid, kBlock, 0, s>>>(V + int64_t(j) * n, w, n, partial + j * kDotGrid);
-  PCHEB_HIP_CHECK(hipGetLastError());
-  host.resize(size_t(m) * kDotGrid);
-  PCHEB_HIP_CHECK(hipMemcpyAsync(host.data(), partial, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  PCHEB_HIP_CHECK(hipStreamSynchronize(s));
-  out.assign(size_t(m), 0.0);
-  for (int j = 0; j < m; ++j)
-    for (int b = 0; b < kDotGrid; ++b) out[size_t(j)] += host[size_t(j) * kDotGrid + size_t(b)];
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal (a, b) (Sturm count).
@@ -92,39 +179,71 @@ static double tridiag_eig(const std::vector<double>& a, const std::vector<double
 static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double* lmax, hipStream_t s) {
   const int64_t n = h.n;
   const int m = int(std::min<int64_t>(steps, n));
-  double* V = static_cast<double*>(dev_alloc(h, size_t(m + 1) * size_t(n) * sizeof(double)));
+  const int64_t ldv = (n + 1) / 2 * 2;  // columns 16-byte aligned
+  double* V = static_cast<double*>(dev_alloc(h, size_t(m + 1) * size_t(ldv) * sizeof(double)));
   double* w = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
   double* isd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
-  double* partial = static_cast<double*>(dev_alloc(h, size_t(m + 1) * kDotGrid * sizeof(double)));
-  double* coef = static_cast<double*>(dev_alloc(h, size_t(m + 1) * sizeof(double)));
+  double* partial = static_cast<double*>(dev_alloc(h, size_t(kCols) * kLzGrid * sizeof(double)));
+  // coefficients c (m + 1), alpha (m), beta (m), 1/beta (1), ||v0|| (1)
+  double* scal = static_cast<double*>(dev_alloc(h, size_t(3 * m + 3) * sizeof(double)));
+  double* coef = scal;
+  double* alpha = scal + (m + 1);
+  double* beta = alpha + m;
+  double* inv = beta + m;
+  double* nrm0 = inv + 1;
   const uint32_t g = 2048;
   k_isqrt_diag<<<g, kBlock, 0, s>>>(h.invd, 1.0 / 6.0, isd, n);
-  std::vector<double> host, out;
-  dots(v0, 1, v0, n, partial, host, out, s);
-  if (!(out[0] > 0.0) || !std::isfinite(out[0])) fail(PCHEB_INVALID, "start vector must be nonzero and finite");
-  k_scale_copy<<<g, kBlock, 0, s>>>(v0, V, 1.0 / std::sqrt(out[0]), n);
-  std::vector<double> alpha, beta;
-  for (int j = 0; j < m; ++j) {
-    const double* vj = V + int64_t(j) * n;
-    launch_ahat(h, InScaled{vj, isd, n}, EpiScaledStore{w, isd, nullptr, nullptr, n}, 0, 1, s);
-    PCHEB_HIP_CHECK(hipGetLastError());
-    dots(vj, 1, w, n, partial, host, out, s);
-    alpha.push_back(out[0]);
-    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-      std::vector<double> c;
-      dots(V, j + 1, w, n, partial, host, c, s);
-      PCHEB_HIP_CHECK(hipMemcpyAsync(coef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      k_sub_combination<<<g, kBlock, 0, s>>>(w, V, coef, j + 1, n);
-    }
-    dots(w, 1, w, n, partial, host, out, s);
-    const double bj = std::sqrt(std::max(0.0, out[0]));
-    if (j + 1 == m || bj <= 1e-14 * std::fabs(alpha.back())) break;
-    beta.push_back(bj);
-    k_scale_copy<<<g, kBlock, 0, s>>>(w, V + int64_t(j + 1) * n, 1.0 / bj, n);
-  }
+
+  // v_0 = v0 / ||v0|| (the one host check: a zero or non-finite start vector is an error)
+  k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(v0, 0, 0, 1, v0, n, partial);
+  k_lz_finalize<<<1, kBlock, 0, s>>>(partial, 1, nullptr, 0, nullptr, 0, nrm0, inv);
+  double nrm = 0.0;
+  PCHEB_HIP_CHECK(hipMemcpyAsync(&nrm, nrm0, sizeof(double), hipMemcpyDeviceToHost, s));
   PCHEB_HIP_CHECK(hipStreamSynchronize(s));
-  *lmin = tridiag_eig(alpha, beta, 1);
-  *lmax = tridiag_eig(alpha, beta, int(alpha.size()));
+  if (!(nrm > 0.0) || !std::isfinite(nrm)) fail(PCHEB_INVALID, "start vector must be nonzero and finite");
+  k_lz_scale<<<g, kBlock, 0, s>>>(v0, V, inv, n);
+
+  for (int j = 0; j < m; ++j) {
+    const double* vj = V + int64_t(j) * ldv;
+    const int cols = j + 1;
+    launch_ahat(h, InScaled{vj, isd, n}, EpiScaledStore{w, isd, nullptr, nullptr, n}, 0, 1, s);
+    // pass 1: c = V^T w (alpha_j = c[j]); then w -= V c
+    for (int c0 = 0; c0 < cols; c0 += kCols) {
+      const int nc = std::min(kCols, cols - c0);
+      k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(V, ldv, c0, nc, w, n, partial);
+      k_lz_finalize<<<1, kBlock, 0, s>>>(partial, nc, coef, c0, alpha, j, nullptr, nullptr);
+    }
+    if (cols <= kCols) {  // first update fused with the second pass's dot products
+      k_lz_update<true, false><<<kLzGrid, kBlock, 0, s>>>(V, ldv, cols, coef, w, n, partial);
+      k_lz_finalize<<<1, kBlock, 0, s>>>(partial, cols, coef, 0, nullptr, j, nullptr, nullptr);
+    } else {
+      k_lz_update<false, false><<<kLzGrid, kBlock, 0, s>>>(V, ldv, cols, coef, w, n, partial);
+      for (int c0 = 0; c0 < cols; c0 += kCols) {
+        const int nc = std::min(kCols, cols - c0);
+        k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(V, ldv, c0, nc, w, n, partial);
+        k_lz_finalize<<<1, kBlock, 0, s>>>(partial, nc, coef, c0, nullptr, j, nullptr, nullptr);
+      }
+    }
+    // pass 2 update with the norm: beta_j = ||w||
+    k_lz_update<false, true><<<kLzGrid, kBlock, 0, s>>>(V, ldv, cols, coef, w, n, partial);
+    k_lz_finalize<<<1, kBlock, 0, s>>>(partial, 1, nullptr, 0, nullptr, j, beta + j, inv);
+    if (j + 1 < m) k_lz_scale<<<g, kBlock, 0, s>>>(w, V + int64_t(j + 1) * ldv, inv, n);
+    PCHEB_HIP_CHECK(hipGetLastError());
+  }
+  std::vector<double> a(static_cast<size_t>(m)), b(static_cast<size_t>(m));
+  PCHEB_HIP_CHECK(hipMemcpyAsync(a.data(), alpha, size_t(m) * sizeof(double), hipMemcpyDeviceToHost, s));
+  PCHEB_HIP_CHECK(hipMemcpyAsync(b.data(), beta, size_t(m) * sizeof(double), hipMemcpyDeviceToHost, s));
+  PCHEB_HIP_CHECK(hipStreamSynchronize(s));
+  int used = m;
+  for (int j = 0; j + 1 < m; ++j)
+    if (!(b[size_t(j)] > 1e-14 * std::fabs(a[size_t(j)]))) {
+      used = j + 1;
+      break;
+    }
+  a.resize(size_t(used));
+  b.resize(size_t(used > 0 ? used - 1 : 0));
+  *lmin = tridiag_eig(a, b, 1);
+  *lmax = tridiag_eig(a, b, used);
 }
 
 }  // namespace pcheb
@@ -136,6 +255,7 @@ extern "C" pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const dou
   try {
     set_last_error("");
     if (!A || !v0 || !lambda_min || !lambda_max) fail(PCHEB_INVALID, "null argument");
+    if (reinterpret_cast<uintptr_t>(v0) % 16 != 0) fail(PCHEB_INVALID, "v0 must be 16-byte aligned");
     if (nsteps < 1 || nsteps > 1000) fail(PCHEB_INVALID, "nsteps must be in [1, 1000]");
     if (A->n <= 0) fail(PCHEB_INVALID, "n must be positive");
     if ((A->kind == PCHEB_OP_CSR || A->kind == PCHEB_OP_SELL) && (!A->rowptr || !A->colind || !A->values))
@@ -158,6 +278,7 @@ extern "C" pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const dou
       release(h);
       throw;
     }
+    (void)hipStreamSynchronize(stream);
     release(h);
     return PCHEB_OK;
   } catch (const Error& e) {

@@ -136,6 +136,22 @@ def test_lanczos_bounds_match_oracle(pc, name):
     assert abs(lo - lo_ref) <= 1e-9 * abs(lo_ref) and abs(hi - hi_ref) <= 1e-9 * hi_ref, (lo, lo_ref, hi, hi_ref)
 
 
+@pytest.mark.parametrize("dims,steps", [((29, 23, 21), 40), ((2, 2, 2), 30), ((3, 2, 1), 12)])
+def test_lanczos_long_and_exhausted(pc, dims, steps):
+    """More basis vectors than one dot-product pass holds (40 > 32), and Krylov spaces
+    that are exhausted before the requested steps (8 and 6 unknowns): the tridiagonal
+    stops at the first vanishing beta, as the oracle's does."""
+    rp, ci, v = W.stencil7_csr(*dims)
+    n = len(rp) - 1
+    v0 = W.uniform(7, n, 0.5, 1.5)
+    a, _ = oracle.jacobi_scale(oracle.csr(rp, ci, v))
+    lo_ref, hi_ref = oracle.lanczos_extremes(lambda x: a @ x, v0, steps)
+    lo, hi = pc.pcheb_estimate_bounds(pc.Operator.stencil7(*dims), _t(v0), steps)
+    assert abs(lo - lo_ref) <= 1e-9 * abs(lo_ref) and abs(hi - hi_ref) <= 1e-9 * hi_ref, (lo, lo_ref, hi, hi_ref)
+    exact_lo, exact_hi = W.stencil7_bounds(*dims)
+    assert exact_lo - 1e-12 <= lo and hi <= exact_hi + 1e-12
+
+
 def test_zero_rhs(pc):
     c = case("st7")
     with pc.pcheb_setup(c.operator(torch, DEV), 5, c.lo, c.hi) as h:
