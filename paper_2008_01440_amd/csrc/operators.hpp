@@ -252,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
     const int64_t base = chunk_ptr[chunk];
     const int32_t len = chunk_len[chunk];
     acc sum = acc(0);
-    for (int32_t j = 0; j < len; ++j) {
+#pragma unroll 8
+    for (int32_t j = 0; j < len; ++j) {  // unrolled: several slots' loads in flight, same summation order
       const int64_t e = base + int64_t(j) * kWave + lane;
       sum += acc(Store<Tv>::ld(val, e)) * in.ld(col[e]);
     }
