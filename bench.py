@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     ap.add_argument("--serve-k", type=int, default=30)
     ap.add_argument("--serve-prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--paper-scale", default="",
+                    help="comma-separated nx of lap3d(nx) solves at the paper's sizes (e.g. 512,1024)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -109,6 +111,10 @@ def main():
     if args.serve:
         for rate in args.serve_rates.split(","):
             run_serve(args, float(rate), torch, pc, W, dev)
+        return
+    if args.paper_scale:
+        for nx in (int(v) for v in args.paper_scale.split(",")):
+            run_paper_scale(nx, torch, pc, W, dev)
         return
     n1 = args.n
     n = n1 ** 3
@@ -274,6 +280,49 @@ def main():
         base = variants["fp64_plain_pcg"]["solves_per_s"]
         out["speedup_vs_fp64_plain_pcg"] = round(flag["solves_per_s"] / base, 3)
     print(json.dumps(out))
+
+
+def run_paper_scale(nx, torch, pc, W, dev):
+    """lap3d(nx): the 7-point Poisson problem of the paper's large runs, (nx - 1)^3 unknowns,
+    matrix-free, s = 1.001, tol 1e-8, x0 = 0, closed-form bounds (a Lanczos basis does not fit
+    at 1023^3), degrees k = 2^nlev - 1 for nlev in {5, 2, 0}.  Right-hand sides: b = A_hat 1
+    (x* = ones) and b ~ U[0, 1] (SplitMix64 seed 0), both formed on the device.  One solve per
+    case (the first includes the capture of its iteration graph); prints a JSON line per case."""
+    N = nx - 1
+    n = N ** 3
+    op = pc.Operator.stencil7(N)
+    lo, hi = W.stencil7_bounds(N)
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    cases = [(5, "f32", 4, True), (5, "f64", 3, False), (2, "f32", 1, True), (0, "f64", 1, False)]
+    for rhs in ("ones", "uniform01"):
+        if rhs == "ones":
+            x.fill_(1.0)
+            with pc.pcheb_setup(op, 0, lo, hi) as h0:
+                pc.pcheb_matvec(h0, x, b)
+        else:
+            pc.pcheb_fill_uniform(b, 0, 0.0, 1.0)
+        torch.cuda.synchronize()
+        for nlev, prec, fuse, flexible in cases:
+            k = 2 ** nlev - 1
+            t0 = time.perf_counter()
+            h = pc.pcheb_setup(op, k, lo, hi, 1.001, prec, fuse_steps=fuse)
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = pc.pcg_solve(h, b, x, tol=1e-8, maxit=20000, flexible=flexible)
+            torch.cuda.synchronize()
+            solve_s = time.perf_counter() - t0
+            pc.pcheb_destroy(h)
+            print(json.dumps({"mode": "paper_scale", "problem": f"lap3d({nx})", "n": n, "rhs": rhs, "nlev": nlev,
+                              "k": k, "prec": prec, "steps_per_pass": fuse, "flexible": flexible,
+                              "iters": st["iters"], "status": st["status"], "solve_s": round(solve_s, 3),
+                              "setup_s": round(setup_s, 3), "relres_true": st["relres_true"],
+                              "n_spmv": st["n_spmv"], "n_dot": st["n_dot"]}), flush=True)
+    del b, x
+    torch.cuda.empty_cache()
 
 
 def run_serve(args, rate, torch, pc, W, dev):
