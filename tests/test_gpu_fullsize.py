@@ -1,0 +1,187 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configuration
+the benchmark times, on sampled outputs.
+
+P_k(A) is a polynomial of degree k in a local operator, so z_i depends only on
+the points within k operator steps of i.  The oracle computes a sampled z_i
+on a box of half-width k + 2 around i (clipped at the grid): the box operator
+differs from the global one only in rows on the box boundary (missing
+neighbours, and for the 27-point operator a ghost treatment of the cells
+beyond the box), and those differences reach at most k points inward.  Samples
+sit at grid corners, in the interior and on the tile and z-range boundaries of
+the fused pass (64 x 32 tiles, 32-plane ranges on 256^3).
+
+The full-size solve is checked through properties that hold at any size: its
+true residual, recomputed on the host with a plain numpy stencil, meets the
+tolerance.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-11, "f32": 5e-5, "bf16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import paper_2008_01440_amd as pc
+    pc.load_library()
+    return pc
+
+
+def _box(centre, dims, w):
+    """Slices (z, y, x) of the box of half-width w around centre (x, y, z), clipped, and
+    the centre's index inside the box."""
+    sl, loc = [], []
+    for c, d in zip(reversed(centre), reversed(dims)):  # z, y, x
+        a, b = max(0, c - w), min(d, c + w + 1)
+        sl.append(slice(a, b))
+        loc.append(c - a)
+    return tuple(sl), tuple(loc)
+
+
+def _sampled_apply(rp_box_fn, r3, centre, dims, k, lo, hi, s=1.001):
+    w = k + 2
+    sl, loc = _box(centre, dims, w)
+    rb = r3[sl]
+    rp, ci, v = rp_box_fn(sl, rb.shape)
+    zb = oracle.nc_apply_unscaled(rp, ci, v, rb.ravel(), lo, hi, k, s).reshape(rb.shape)
+    return zb[loc], float(np.abs(zb).max())
+
+
+SAMPLES_256 = [(0, 0, 0), (255, 255, 255), (128, 128, 128), (63, 31, 31), (64, 32, 32), (127, 200, 95),
+               (255, 0, 160)]
+
+
+@pytest.mark.parametrize("prec,fuse", [("f32", 4), ("f64", 3)])
+def test_apply_256_sampled(pc, prec, fuse):
+    """256^3 7-point, k = 50 (the benchmark's apply: F32, four steps per pass)."""
+    N, k = 256, 50
+    dims = (N, N, N)
+    lo, hi = W.stencil7_bounds(N)
+    hi *= 1.01
+    r = W.uniform(5, N ** 3, -1.0, 1.0)
+    with pc.pcheb_setup(pc.Operator.stencil7(N), k, lo, hi, 1.001, prec, fuse_steps=fuse) as h:
+        z = torch.empty(N ** 3, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, torch.from_numpy(r).to(DEV), z)
+        torch.cuda.synchronize()
+    zg = z.cpu().numpy().reshape(N, N, N)
+    r3 = r.reshape(N, N, N)
+    for c in SAMPLES_256:
+        zr, scale = _sampled_apply(lambda sl, shp: W.stencil7_csr(shp[2], shp[1], shp[0]), r3, c, dims, k, lo, hi)
+        got = zg[c[2], c[1], c[0]]
+        assert abs(got - zr) <= TOL[prec] * scale, (prec, c, got, zr, scale)
+
+
+SAMPLES_192 = [(0, 0, 0), (191, 191, 191), (96, 96, 96), (63, 3, 7), (64, 4, 8), (10, 150, 190)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f64"])
+def test_apply_192_h27_sampled(pc, prec):
+    """192^3 27-point harmonic operator with lognormal(0, 2) cell coefficients, k = 20.
+    Both sides use the fixed interval [1e-4, 2] (it contains the Jacobi-scaled operator's
+    spectrum, which lies in (0, 2]): parity needs the same polynomial, not tight bounds."""
+    N, k = 192, 20
+    dims = (N, N, N)
+    kappa = W.harmonic27_kappa(N, N, N, seed=1)
+    op = pc.Operator.stencil27h(torch.from_numpy(kappa).to(DEV))
+    lo, hi = 1e-4, 2.0
+    r = W.uniform(5, N ** 3, -1.0, 1.0)
+    with pc.pcheb_setup(op, k, lo, hi, 1.001, prec) as h:
+        z = torch.empty(N ** 3, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, torch.from_numpy(r).to(DEV), z)
+        torch.cuda.synchronize()
+    zg = z.cpu().numpy().reshape(N, N, N)
+    r3 = r.reshape(N, N, N)
+    for c in SAMPLES_192:
+        zr, scale = _sampled_apply(lambda sl, shp: W.harmonic27_csr(kappa[sl]), r3, c, dims, k, lo, hi)
+        got = zg[c[2], c[1], c[0]]
+        assert abs(got - zr) <= TOL[prec] * scale, (prec, c, got, zr, scale)
+
+
+def _stencil7(x3):
+    """6 x - (sum of the six neighbours), zero outside the grid (numpy, for the checks only)."""
+    y = 6.0 * x3
+    y[1:, :, :] -= x3[:-1, :, :]
+    y[:-1, :, :] -= x3[1:, :, :]
+    y[:, 1:, :] -= x3[:, :-1, :]
+    y[:, :-1, :] -= x3[:, 1:, :]
+    y[:, :, 1:] -= x3[:, :, :-1]
+    y[:, :, :-1] -= x3[:, :, 1:]
+    return y
+
+
+def test_solve_256_true_residual(pc):
+    """The benchmark's solve (256^3, k = 50, F32, four steps per pass, flexible PCG,
+    Lanczos bounds x1.01): its true residual, recomputed on the host, meets tol."""
+    N, k = 256, 50
+    xs = W.uniform(0, N ** 3, -1.0, 1.0).reshape(N, N, N)
+    b = _stencil7(xs)
+    op = pc.Operator.stencil7(N)
+    v0 = torch.empty(N ** 3, dtype=torch.float64, device=DEV)
+    pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+    lo, hi = pc.pcheb_estimate_bounds(op, v0, 30)
+    del v0
+    exact_lo, exact_hi = W.stencil7_bounds(N)
+    assert exact_lo <= lo and hi <= exact_hi  # Ritz values lie inside the spectrum
+    with pc.pcheb_setup(op, k, lo, 1.01 * hi, 1.001, "f32", fuse_steps=4) as h:
+        x = torch.zeros(N ** 3, dtype=torch.float64, device=DEV)
+        st = pc.pcg_solve(h, torch.from_numpy(b.ravel()).to(DEV), x, tol=1e-8, flexible=True)
+    xg = x.cpu().numpy().reshape(N, N, N)
+    res = np.linalg.norm(b - _stencil7(xg)) / np.linalg.norm(b)  # D = 6 I: weighted = unweighted
+    assert st["status"] == "OK" and res <= 1.02e-8, (st, res)
+    assert abs(res - st["relres_true"]) <= 1e-3 * res  # the library's own exit check agrees
+    err = np.linalg.norm(xg - xs) / np.linalg.norm(xs)
+    assert err <= 26768.0 * 1.02e-8  # kappa(A) times the residual bound
+
+
+SAMPLES_EL = [0, 63, 100, 127]  # free-node index on the diagonal (cubic clipped boxes)
+
+
+@functools.lru_cache(maxsize=1)
+def _elasticity_128():
+    emod = W.elasticity_q1_moduli(128, seed=2)
+    return (emod,) + tuple(W.elasticity_q1_csr(128, moduli=emod))
+
+
+@pytest.mark.parametrize("fmt", ["sell256", "csr"])
+def test_apply_elasticity_128_sampled(pc, fmt):
+    """Q1 elasticity, 128^3 free nodes x 3 (502M nonzeros), k = 20, F32 recurrence, stored as
+    CSR or SELL-C-sigma (C = 64, sigma = 256).  The oracle's box operator comes from the same
+    generator on the elements around the box, with moduli scaled so that the box's element
+    size gives the global matrix entries.  Fixed interval [1e-4, 2] on both sides."""
+    N, k = 128, 20
+    emod, rp, ci, v = _elasticity_128()
+    n = len(rp) - 1
+    d = [torch.from_numpy(a).to(DEV) for a in (rp, ci, v)]
+    op = pc.Operator.csr(*d, sell=fmt != "csr", sigma=256)
+    lo, hi = 1e-4, 2.0
+    r = W.uniform(5, n, -1.0, 1.0)
+    with pc.pcheb_setup(op, k, lo, hi, 1.001, "f32") as h:
+        z = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, torch.from_numpy(r).to(DEV), z)
+        torch.cuda.synchronize()
+    del d
+    zg = z.cpu().numpy().reshape(N, N, N, 3)
+    r4 = r.reshape(N, N, N, 3)
+    w = k + 2
+    for c in SAMPLES_EL:
+        a, b = max(0, c - w), min(N, c + w + 1)
+        m = b - a
+        box_mod = emod[a:b + 1, a:b + 1, a:b + 1] * ((m + 1) / (N + 1))  # h_global / h_box
+        brp, bci, bv = W.elasticity_q1_csr(m, moduli=box_mod)
+        rb = r4[a:b, a:b, a:b].ravel()
+        zb = oracle.nc_apply_unscaled(brp, bci, bv, rb, lo, hi, k, 1.001).reshape(m, m, m, 3)
+        loc = c - a
+        scale = float(np.abs(zb).max())
+        got, ref = zg[c, c, c], zb[loc, loc, loc]
+        assert np.abs(got - ref).max() <= TOL["f32"] * scale, (fmt, c, got, ref, scale)
