@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     ap.add_argument("--serve-k", type=int, default=30)
     ap.add_argument("--serve-prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--configs", default="",
+                    help="comma-separated subset of c1,c2,c3,c4: per-configuration measurements, one JSON line each")
     ap.add_argument("--paper-scale", default="",
                     help="comma-separated nx of lap3d(nx) solves at the paper's sizes (e.g. 512,1024)")
     args = ap.parse_args()
@@ -115,6 +117,12 @@ def main():
     if args.paper_scale:
         for nx in (int(v) for v in args.paper_scale.split(",")):
             run_paper_scale(nx, torch, pc, W, dev)
+        return
+    configs = [c for c in args.configs.split(",") if c]
+    for c in configs:
+        if c != "c2":
+            {"c1": run_c1, "c3": run_c3, "c4": run_c4}[c](torch, pc, W, dev)
+    if configs and "c2" not in configs:
         return
     n1 = args.n
     n = n1 ** 3
@@ -184,6 +192,23 @@ def main():
             f"iters={st['iters']:5d} relres_true={st['relres_true']:.2e} err={err:.2e}"
             + (f"  step {res['step_avg_us']:.1f} us" if step_n else ""))
         return res
+
+    if "c2" in configs:
+        rows = []
+        for k in (0, 5, 20, 50, 100):
+            for kind, prec, fuse in (("stencil7", "f64", 3), ("stencil7", "f32", 4), ("stencil7", "bf16", 4),
+                                     ("csr", "f64", 1), ("csr", "f32", 1)):
+                if k == 0 and prec != "f64":
+                    continue
+                r = run(kind, k, prec, 2, 1, flexible=prec != "f64", time_kernels=k >= 3, fuse=fuse if k >= 3 else 1)
+                e = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+                if r["step_avg_us"]:
+                    step_bytes = 4 * e * n if kind == "stencil7" else (e + 4) * int(rp[-1]) + 4 * (n + 1) + 4 * e * n
+                    r["step_alg_gbs"] = round(step_bytes / (r["step_avg_us"] * 1e-6) / 1e9, 1)
+                rows.append(r)
+        print(json.dumps({"config": "c2", "workload": f"3-D 7-point Poisson {n1}^3, Lanczos(30) bounds x1.01, "
+                          "b = A x*, tol 1e-8; matrix-free and CSR", "rows": rows}), flush=True)
+        return
 
     if args.sweep:
         rows = []
@@ -280,6 +305,134 @@ def main():
         base = variants["fp64_plain_pcg"]["solves_per_s"]
         out["speedup_vs_fp64_plain_pcg"] = round(flag["solves_per_s"] / base, 3)
     print(json.dumps(out))
+
+
+def _timed_solves(torch, pc, h, b, reps, flexible, time_kernels=False, warmup=1):
+    x = torch.zeros_like(b)
+    for _ in range(warmup):
+        pc.pcg_solve(h, b, x, tol=1e-8, maxit=50000, flexible=flexible, time_kernels=time_kernels)
+    torch.cuda.synchronize()
+    lat, st = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        st = pc.pcg_solve(h, b, x, tol=1e-8, maxit=50000, flexible=flexible, time_kernels=time_kernels)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    return st, x, lat
+
+
+def run_c1(torch, pc, W, dev):
+    """32^3 7-point Poisson, CSR FP64, k = 10, exact closed-form bounds, tol 1e-8: GPU solve
+    latency, and the FP64 oracle's CPU seconds for the same solve on 1 and on all host cores."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+
+    N, k = 32, 10
+    rp, ci, v = W.stencil7_csr(N)
+    n = N ** 3
+    xs = W.uniform(0, n, -1.0, 1.0)
+    b = W.rhs_from_solution(rp, ci, v, xs)
+    lo, hi = W.stencil7_bounds(N)
+    d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v)]
+    bt = torch.from_numpy(b).to(dev)
+    with pc.pcheb_setup(pc.Operator.csr(*d), k, lo, hi, 1.001, "f64") as h:
+        st, x, lat = _timed_solves(torch, pc, h, bt, 50, False, warmup=3)
+    err = float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
+    cpu = {}
+    cores = os.cpu_count() or 1
+    for label, lim in (("1", 1), ("all", cores)):
+        with threadpool_limits(limits=lim):
+            t0 = time.perf_counter()
+            ref = oracle.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8)
+            cpu[label] = time.perf_counter() - t0
+    print(json.dumps({"config": "c1", "workload": "3-D 7-point Poisson 32^3, CSR FP64, k=10, closed-form bounds, "
+                      "b = A x*, tol 1e-8", "gpu_p50_ms": round(1e3 * percentile(lat, 50), 3),
+                      "gpu_p99_ms": round(1e3 * percentile(lat, 99), 3), "gpu_solves_per_s": round(len(lat) / sum(lat), 1),
+                      "gpu_iters": st["iters"], "oracle_iters": ref.iters, "err_vs_xstar": err,
+                      "relres_true": st["relres_true"], "oracle_cpu_s_1core": round(cpu["1"], 4),
+                      f"oracle_cpu_s_{cores}threads": round(cpu["all"], 4), "host_cores": cores}), flush=True)
+
+
+def run_c3(torch, pc, W, dev):
+    """192^3 27-point harmonic diffusion, lognormal(0, 2) cells: k in {10, 20, 40, 80} with the
+    recurrence in F64, F32 and BF16 (F32 arithmetic), FP64 flexible PCG; errors of the mixed
+    solutions against the F64 one."""
+    N = 192
+    n = N ** 3
+    kappa = torch.from_numpy(W.harmonic27_kappa(N, N, N, seed=1)).to(dev)
+    op = pc.Operator.stencil27h(kappa)
+    xs = torch.empty(n, dtype=torch.float64, device=dev)
+    pc.pcheb_fill_uniform(xs, 0, -1.0, 1.0)
+    b = torch.empty_like(xs)
+    v0 = torch.empty_like(xs)
+    pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+    lo, hi = pc.pcheb_estimate_bounds(op, v0, 30)
+    hi *= 1.01
+    del v0
+    rows = []
+    with pc.pcheb_setup(op, 0, lo, hi) as h0:
+        pc.pcheb_matvec(h0, xs, b)
+        st, x, lat = _timed_solves(torch, pc, h0, b, 1, False)
+        rows.append({"k": 0, "prec": "f64", "iters": st["iters"], "solves_per_s": round(1 / lat[0], 3),
+                     "relres_true": st["relres_true"]})
+    for k in (10, 20, 40, 80):
+        x64 = None
+        for prec in ("f64", "f32", "bf16"):
+            with pc.pcheb_setup(op, k, lo, hi, 1.001, prec) as h:
+                st, x, lat = _timed_solves(torch, pc, h, b, 2, prec != "f64", time_kernels=True)
+            e = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+            step_bytes = 4 * e * n + 8 * n  # iterates + operator data (kappa, or 1/(2 kappa) and D^-1 in float)
+            row = {"k": k, "prec": prec, "iters": st["iters"], "solves_per_s": round(2 / sum(lat), 3),
+                   "relres_true": st["relres_true"], "step_us": round(st["step_ms"] * 1e3 / max(1, st["step_launches"]), 2),
+                   "err_vs_xstar": float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))}
+            row["step_alg_gbs"] = round(step_bytes / (row["step_us"] * 1e-6) / 1e9, 1) if row["step_us"] else None
+            if prec == "f64":
+                x64 = x.clone()
+            else:
+                row["rel_diff_vs_f64_solution"] = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+            rows.append(row)
+            log(f"  c3 k={k} {prec}: {row}")
+    print(json.dumps({"config": "c3", "workload": "27-point harmonic diffusion 192^3, lognormal(0,2) cells seed 1, "
+                      "Lanczos(30) bounds x1.01, b = A x*, tol 1e-8", "lambda_min": lo, "lambda_max": hi,
+                      "kappa_estimate": hi / lo, "rows": rows}), flush=True)
+
+
+def run_c4(torch, pc, W, dev):
+    """Q1 elasticity 128^3 x 3 (502M nonzeros): F32 recurrence with k in {20, 60} stored as CSR and
+    as SELL-C-sigma (C = 64, sigma = 256), FP64 flexible PCG; FP64 plain PCG (k = 0) beside."""
+    N = 128
+    rp, ci, v = W.elasticity_q1_csr(N, seed=2)
+    n = len(rp) - 1
+    nnz = int(rp[-1])
+    xs_h = W.uniform(0, n, -1.0, 1.0)
+    b = torch.from_numpy(W.rhs_from_solution(rp, ci, v, xs_h)).to(dev)
+    xs = torch.from_numpy(xs_h).to(dev)
+    d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v)]
+    del rp, ci, v, xs_h
+    v0 = torch.empty(n, dtype=torch.float64, device=dev)
+    pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+    lo, hi = pc.pcheb_estimate_bounds(pc.Operator.csr(*d), v0, 30)
+    hi *= 1.01
+    del v0
+    rows = []
+    for fmt in ("sell256", "csr"):
+        op = pc.Operator.csr(*d, sell=fmt != "csr", sigma=256)
+        cases = [(0, "f64"), (20, "f32"), (60, "f32")] if fmt == "sell256" else [(20, "f32"), (60, "f32")]
+        for k, prec in cases:
+            with pc.pcheb_setup(op, k, lo, hi, 1.001, prec) as h:
+                st, x, lat = _timed_solves(torch, pc, h, b, 1, prec != "f64", time_kernels=k >= 3)
+            row = {"format": fmt, "k": k, "prec": prec, "iters": st["iters"], "solve_s": round(lat[0], 3),
+                   "relres_true": st["relres_true"],
+                   "err_vs_xstar": float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))}
+            if k >= 3 and st["step_launches"]:
+                row["step_us"] = round(st["step_ms"] * 1e3 / st["step_launches"], 1)
+                step_bytes = 8 * nnz + 4 * (n + 1) + 16 * n
+                row["step_alg_gbs"] = round(step_bytes / (row["step_us"] * 1e-6) / 1e9, 1)
+            rows.append(row)
+            log(f"  c4 {row}")
+    print(json.dumps({"config": "c4", "workload": "Q1 elasticity 128^3 free nodes x 3, E = 1 +- 10% seed 2, nu 0.3, "
+                      "Lanczos(30) bounds x1.01, b = A x*, tol 1e-8", "n": n, "nnz": nnz, "lambda_min": lo,
+                      "lambda_max": hi, "rows": rows}), flush=True)
 
 
 def run_paper_scale(nx, torch, pc, W, dev):

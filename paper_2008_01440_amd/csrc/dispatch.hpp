@@ -44,14 +44,15 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     case PCHEB_OP_STENCIL27H: {
       const StencilGrid g = stencil_grid(op);
       grid = g.grid;
-      const acc* kappa = nullptr;
       if constexpr (sizeof(acc) == 8) {
-        kappa = reinterpret_cast<const acc*>(op.cell_coeff);
+        k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
+            in, epi, reinterpret_cast<const acc*>(op.cell_coeff), op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y,
+            g.ntiles, h.rb(), slot0);
       } else {
-        kappa = reinterpret_cast<const acc*>(h.kappa_lo);
+        static_assert(SCALED || sizeof(acc) == 8, "float arithmetic is used for D^-1 A_hat only");
+        k_stencil27h_lo<kZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
+            in, epi, h.rho_lo, h.invd_lo, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       }
-      k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
-          in, epi, kappa, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_CSR: {

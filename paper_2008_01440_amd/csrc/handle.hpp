@@ -53,7 +53,8 @@ struct Handle {
   double* sell_aval = nullptr;  // A_hat values (float64)
   void* sell_bval = nullptr;    // D^-1 A_hat values (storage precision)
   int32_t* sell_perm = nullptr; // null when sigma == 1
-  void* kappa_lo = nullptr;     // STENCIL27H: float32 copy of the coefficients
+  float* rho_lo = nullptr;      // STENCIL27H, float recurrences: 1 / (2 kappa) per cell
+  float* invd_lo = nullptr;     // STENCIL27H, float recurrences: D^-1 rounded to float
 
   // solve workspace for `cap` right-hand sides (slots); vectors of slot j start
   // at j * ldw elements.  Allocated on demand, separately from the operator data.

@@ -14,7 +14,8 @@
 // results are the same alone and batched.
 //
 // Interfaces
-//   In:  using acc; int64_t stride; __device__ void bind(int slot); __device__ void prepare();
+//   In:  using acc; static constexpr bool narrow (loads need a conversion); int64_t stride;
+//        __device__ void bind(int slot); __device__ void prepare();
 //        __device__ acc ld(int64_t i) const;
 //   Epi: using acc; static constexpr int NV; static constexpr bool reduce;
 //        DevState* st (may be null; written by fin); const DevState* guard (may be
@@ -89,14 +90,25 @@ __global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int
     if (x >= nx || y >= ny) continue;
     const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
     int64_t i = x + int64_t(nx) * y + plane * z0;
-    acc below = z0 > 0 ? in.ld(i - plane) : acc(0);
+    // Neighbours outside the grid read as zero.  Narrow (BF16) inputs are
+    // loaded from a valid address (the point itself) and zeroed by a select:
+    // with a branch around each load, each conversion would wait for its load.
+    auto nb = [&](bool ok, int64_t j, int64_t self) {
+      if constexpr (In::narrow) {
+        const acc v = in.ld(ok ? j : self);
+        return ok ? v : acc(0);
+      } else {
+        return ok ? in.ld(j) : acc(0);
+      }
+    };
+    acc below = nb(z0 > 0, i - plane, i);
     acc centre = in.ld(i);
     for (int z = z0; z < z1; ++z, i += plane) {
-      const acc above = z + 1 < nz ? in.ld(i + plane) : acc(0);
-      const acc w = x > 0 ? in.ld(i - 1) : acc(0);
-      const acc e = x + 1 < nx ? in.ld(i + 1) : acc(0);
-      const acc s = y > 0 ? in.ld(i - nx) : acc(0);
-      const acc n = y + 1 < ny ? in.ld(i + nx) : acc(0);
+      const acc above = nb(z + 1 < nz, i + plane, i);
+      const acc w = nb(x > 0, i - 1, i);
+      const acc e = nb(x + 1 < nx, i + 1, i);
+      const acc s = nb(y > 0, i - nx, i);
+      const acc n = nb(y + 1 < ny, i + nx, i);
       const acc nb = ((w + e) + (s + n)) + (below + above);
       const acc m = SCALED ? centre - nb * acc(1.0 / 6.0) : acc(6) * centre - nb;
       epi(i, centre, m, part);
@@ -108,6 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int
 }
 
 // ------------------------------------------------------------------ 27-point harmonic stencil
+//
+// Face weights are harmonic means 2 a b / (a + b) of the cell coefficients,
+// recomputed at every product (this kernel runs in double arithmetic; the
+// float recurrences use k_stencil27h_lo below).
 //
 // Same tiling as the 7-point kernel.  Each thread keeps the 3x3 neighbourhood
 // of y and of the cell coefficients for the planes z-1, z, z+1 in registers
@@ -144,9 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT*
         for (int dx = -1; dx <= 1; ++dx) {
           const int xx = x + dx, yy = y + dy;
           const bool ok = zz >= 0 && zz < nz && xx >= 0 && xx < nx && yy >= 0 && yy < ny;
-          const int64_t j = xx + int64_t(nx) * yy + plane * zz;
-          yv[slot][dy + 1][dx + 1] = ok ? in.ld(j) : acc(0);
-          kv[slot][dy + 1][dx + 1] = ok ? acc(kappa[j]) : acc(0);
+          const int64_t j = ok ? xx + int64_t(nx) * yy + plane * zz : x + int64_t(nx) * y;  // clamped, then zeroed
+          const acc yj = in.ld(j);
+          const acc kj = acc(kappa[j]);
+          yv[slot][dy + 1][dx + 1] = ok ? yj : acc(0);
+          kv[slot][dy + 1][dx + 1] = ok ? kj : acc(0);
         }
       }
     };
@@ -186,6 +204,93 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT*
           kv[0][dy][dx] = kv[1][dy][dx];
           yv[1][dy][dx] = yv[2][dy][dx];
           kv[1][dy][dx] = kv[2][dy][dx];
+        }
+      }
+    }
+  }
+  finish_reduction(epi, part, rb, slot);
+}
+
+// D^-1 A_hat y in float arithmetic (the F32 / BF16 recurrences).  With
+// rho = 1 / (2 kappa) per cell the face weight is 1 / (rho_i + rho_n): one add
+// and one hardware reciprocal (about 1 ulp) per neighbour.  Cells outside the
+// grid read rho = +inf, so their weight is exactly 0 (a zero-Dirichlet ghost
+// contributes only to the diagonal), and the reciprocal of the diagonal is
+// precomputed from the float64 one, so no branches and no diagonal sum remain.
+template <int ZC, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_stencil27h_lo(In in, Epi epi, const float* __restrict__ rho,
+                                                          const float* __restrict__ invd, int nx, int ny, int nz,
+                                                          uint32_t tiles_x, uint32_t tiles_y, uint32_t ntiles,
+                                                          ReduceBuf rb, int slot0) {
+  static_assert(sizeof(typename Epi::acc) == 4, "float arithmetic only");
+  const int slot = slot0 + int(blockIdx.y);
+  if (bind_slot(in, epi, slot)) return;
+  double part[Epi::NV];
+#pragma unroll
+  for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
+  const int64_t plane = int64_t(nx) * ny;
+  XcdTiles tiles(ntiles);
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const uint32_t tx = t % tiles_x;
+    const uint32_t rest = t / tiles_x;
+    const uint32_t ty = rest % tiles_y;
+    const uint32_t tz = rest / tiles_y;
+    const int x = int(tx) * 64 + int(threadIdx.x);
+    const int y = int(ty) * 4 + int(threadIdx.y);
+    const int z0 = int(tz) * ZC;
+    if (x >= nx || y >= ny) continue;
+    const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
+    float yv[3][3][3];
+    float rv[3][3][3];
+    auto load_plane = [&](int slot, int zz) {
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int xx = x + dx, yy = y + dy;
+          const bool ok = zz >= 0 && zz < nz && xx >= 0 && xx < nx && yy >= 0 && yy < ny;
+          if constexpr (In::narrow) {  // as in k_stencil7: no branch around narrow loads
+            const int64_t j = ok ? xx + int64_t(nx) * yy + plane * zz : x + int64_t(nx) * y;
+            const float yj = float(in.ld(j));
+            const float rj = rho[j];
+            yv[slot][dy + 1][dx + 1] = ok ? yj : 0.0f;
+            rv[slot][dy + 1][dx + 1] = ok ? rj : __builtin_inff();
+          } else {
+            const int64_t j = xx + int64_t(nx) * yy + plane * zz;
+            yv[slot][dy + 1][dx + 1] = ok ? float(in.ld(j)) : 0.0f;
+            rv[slot][dy + 1][dx + 1] = ok ? rho[j] : __builtin_inff();
+          }
+        }
+      }
+    };
+    load_plane(0, z0 - 1);
+    load_plane(1, z0);
+    for (int z = z0; z < z1; ++z) {
+      load_plane(2, z + 1);
+      const float ri = rv[1][1][1];
+      float off = 0.0f;
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            if (dz == 1 && dy == 1 && dx == 1) continue;
+            off += __builtin_amdgcn_rcpf(ri + rv[dz][dy][dx]) * yv[dz][dy][dx];
+          }
+        }
+      }
+      const float yc = yv[1][1][1];
+      const int64_t i = x + int64_t(nx) * y + plane * z;
+      epi(i, yc, yc - off * invd[i], part);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          yv[0][dy][dx] = yv[1][dy][dx];
+          rv[0][dy][dx] = rv[1][dy][dx];
+          yv[1][dy][dx] = yv[2][dy][dx];
+          rv[1][dy][dx] = rv[2][dy][dx];
         }
       }
     }
@@ -270,6 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
 template <class T>
 struct InVec {
   using acc = typename Store<T>::acc;
+  static constexpr bool narrow = sizeof(T) < 4;  // loads need a conversion
   const T* p;
   int64_t stride;
   __device__ __forceinline__ void bind(int slot) { p += slot * stride; }
@@ -280,6 +386,7 @@ struct InVec {
 // p = z + beta * p_old, formed where it is read (beta from the solver state).
 struct InDirection {
   using acc = double;
+  static constexpr bool narrow = false;
   const double* z;
   const double* p_old;
   const DevState* st;
@@ -297,6 +404,7 @@ struct InDirection {
 // v scaled by D^-1/2 (for the symmetric scaled operator of the Lanczos estimator).
 struct InScaled {
   using acc = double;
+  static constexpr bool narrow = false;
   const double* v;
   const double* isd;  // 1 / sqrt(diag), shared by all slots
   int64_t stride;

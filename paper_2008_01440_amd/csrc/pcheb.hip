@@ -96,10 +96,6 @@ __global__ void k_fill(double* p, int64_t n, double v) {
   GRID_STRIDE(i, n) p[i] = v;
 }
 
-__global__ void k_to_float(const double* a, float* b, int64_t n) {
-  GRID_STRIDE(i, n) b[i] = float(a[i]);
-}
-
 // CSR diagonal (sum of entries on the diagonal) -> 1/d; flags d <= 0.
 __global__ void k_csr_invdiag(const int32_t* rowptr, const int32_t* col, const double* val, int64_t n,
                               double* invd, int* bad) {
@@ -144,6 +140,15 @@ __global__ void k_h27_invdiag(const double* kappa, int nx, int ny, int nz, doubl
           }
         }
     invd[i] = 1.0 / d;
+  }
+}
+
+// Operator data of the float recurrences on the 27-point operator: rho = 1 / (2 kappa)
+// and D^-1, both rounded to float.
+__global__ void k_h27_lo(const double* kappa, const double* invd, float* rho, float* invd_lo, int64_t n) {
+  GRID_STRIDE(i, n) {
+    rho[i] = float(0.5 / kappa[i]);
+    invd_lo[i] = float(invd[i]);
   }
 }
 
@@ -736,8 +741,9 @@ void setup_operator(Handle& h, hipStream_t s) {
     h.invd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
     k_h27_invdiag<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, op.nx, op.ny, op.nz, h.invd, bad);
     if (h.prm.prec != PCHEB_F64) {
-      h.kappa_lo = dev_alloc(h, size_t(n) * sizeof(float));
-      k_to_float<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, static_cast<float*>(h.kappa_lo), n);
+      h.rho_lo = static_cast<float*>(dev_alloc(h, size_t(n) * sizeof(float)));
+      h.invd_lo = static_cast<float*>(dev_alloc(h, size_t(n) * sizeof(float)));
+      k_h27_lo<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, h.invd, h.rho_lo, h.invd_lo, n);
     }
   }
   PCHEB_HIP_CHECK(hipGetLastError());
@@ -792,7 +798,7 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
     b += size_t(n) * 8 + size_t(chunks) * 12 + size_t(A->nnz) * (4 + 8 + e);
     if (A->sell_sigma > 1) b += size_t(n) * 4;
   }
-  if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 4 : 0);
+  if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 8 : 0);
   const int ny = (A->kind == PCHEB_OP_STENCIL7 && p->fuse_steps >= 2) ? 4 : 3;
   const size_t per_rhs = size_t(round_up(n, 64)) * ((1 + ny) * e + 5 * 8) + sizeof(DevState) +
                          size_t(kMaxGrid) * kMaxReduce * 8;
