@@ -98,7 +98,20 @@ typedef struct pcheb_operator {
  * (1 gives the min-max optimal polynomial; the paper uses 1.01 and 1.001).
  * fuse_steps > 1 asks the matrix-free stencil paths to run that many
  * recurrence steps per pass over memory (ignored elsewhere; 0 or 1 = off).
+ * form selects how the same polynomial is applied (Theorem 2 makes them
+ * equal in exact arithmetic): PCHEB_FORM_CHEBYSHEV, the three-term
+ * recurrence of Alg. 2 (any k); PCHEB_FORM_NEWTON, the recursion of Alg. 1,
+ * P_0 u = zeta_0 u, P_{j+1} u = zeta_{j+1} (2 P_j u - P_j A P_j u), which
+ * needs k = 2^nlev - 1 (nlev <= 9), F64 or F32 storage (each level evaluates
+ * P_j twice, so stored intermediates compound rounding about 2^nlev-fold,
+ * too much for BF16) and 2 nlev + 1 extra iterate vectors; it does not fuse
+ * steps.
  */
+typedef enum pcheb_form {
+  PCHEB_FORM_CHEBYSHEV = 0,
+  PCHEB_FORM_NEWTON = 1
+} pcheb_form;
+
 typedef struct pcheb_params {
   int32_t k;                /* degree = operator products per application, 0 <= k <= 1000 */
   double lambda_min;
@@ -106,6 +119,7 @@ typedef struct pcheb_params {
   double theta_scale;       /* s >= 1 */
   int32_t prec;             /* pcheb_precision */
   int32_t fuse_steps;
+  int32_t form;             /* pcheb_form */
 } pcheb_params;
 
 /* Flags of pcg_solve. */

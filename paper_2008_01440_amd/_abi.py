@@ -21,6 +21,7 @@ STATUS = {
 
 OP_KIND = {"csr": 0, "sell": 1, "stencil7": 2, "stencil27h": 3}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
+FORM = {"chebyshev": 0, "newton": 1}
 
 PCG_FLEXIBLE = 0x1
 PCG_X0_GIVEN = 0x2
@@ -63,6 +64,7 @@ class CParams(ctypes.Structure):
         ("theta_scale", ctypes.c_double),
         ("prec", ctypes.c_int32),
         ("fuse_steps", ctypes.c_int32),
+        ("form", ctypes.c_int32),
     ]
 
 
@@ -249,15 +251,18 @@ class Handle:
         pcheb_destroy(self)
 
 
-def _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps):
+def _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form="chebyshev"):
     return CParams(k=k, lambda_min=lambda_min, lambda_max=lambda_max, theta_scale=theta_scale,
-                   prec=PREC[prec] if isinstance(prec, str) else int(prec), fuse_steps=fuse_steps)
+                   prec=PREC[prec] if isinstance(prec, str) else int(prec), fuse_steps=fuse_steps,
+                   form=FORM[form] if isinstance(form, str) else int(form))
 
 
 def pcheb_setup(op: Operator, k: int, lambda_min: float, lambda_max: float, theta_scale: float = 1.001,
-                prec: str = "f64", fuse_steps: int = 1, stream=None) -> Handle:
+                prec: str = "f64", fuse_steps: int = 1, stream=None, form: str = "chebyshev") -> Handle:
+    """form: "chebyshev" (the recurrence of Alg. 2) or "newton" (the recursion of Alg. 1,
+    k = 2^nlev - 1)."""
     lib = load_library()
-    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps)
+    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form)
     out = ctypes.c_void_p()
     _check(lib.pcheb_setup(ctypes.byref(op.c), ctypes.byref(p), _stream(stream), ctypes.byref(out)))
     return Handle(out, op, p)
@@ -307,8 +312,9 @@ def pcheb_destroy(h: Handle):
 
 
 def pcheb_footprint_bytes(op: Operator, k: int, lambda_min: float = 0.1, lambda_max: float = 2.0,
-                          theta_scale: float = 1.001, prec: str = "f64", nrhs: int = 1) -> int:
-    p = _params(k, lambda_min, lambda_max, theta_scale, prec, 1)
+                          theta_scale: float = 1.001, prec: str = "f64", nrhs: int = 1, fuse_steps: int = 1,
+                          form: str = "chebyshev") -> int:
+    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form)
     return int(load_library().pcheb_footprint_bytes(ctypes.byref(op.c), ctypes.byref(p), nrhs))
 
 

@@ -40,6 +40,8 @@ struct Handle {
   // Chebyshev scalars (Sec. 3 with the Sec. 4 scaling)
   double theta = 0, delta = 0, sigma = 0;
   std::vector<double> rho;
+  int nlev = 0;               // Newton form: k = 2^nlev - 1
+  std::vector<double> zeta;   // Newton form: zeta_0 .. zeta_nlev
 
   // operator data owned by the handle
   double* invd = nullptr;     // D^-1 (null for the 7-point stencil: constant 1/6)
@@ -61,6 +63,7 @@ struct Handle {
   int cap = 0;
   int64_t ldw = 0;
   int nY = 3;                 // iterate buffers in use (4 when steps are fused)
+  std::vector<void*> nt;      // Newton form: 2 nlev + 1 iterate buffers (cap slots each)
   int fuse = 1;               // recurrence steps per pass (7-point stencil only)
   void* s = nullptr;          // D^-1 r (storage precision)
   void* Y[4] = {nullptr, nullptr, nullptr, nullptr};  // recurrence iterates (storage precision)

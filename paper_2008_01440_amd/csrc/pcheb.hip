@@ -63,6 +63,7 @@ static void release_workspace(Handle& h) {
   h.st_host = nullptr;
   for (auto& b : h.owned_ws) (void)hipFree(b.ptr);
   h.owned_ws.clear();
+  h.nt.clear();
   h.cap = 0;
 }
 
@@ -585,6 +586,10 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
 
 // Stand-alone application r -> z (caller vectors) on slot 0 of the workspace.
 template <class T>
+static void enqueue_newton(Handle& h, Slots sl, double* z, int64_t ldz, const double* r, int64_t ldr,
+                           const double* q, bool dots, int init, int flexible, DevState* guard, hipStream_t s);
+
+template <class T>
 static void enqueue_apply_one(Handle& h, const double* r, double* z, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
@@ -594,7 +599,103 @@ static void enqueue_apply_one(Handle& h, const double* r, double* z, hipStream_t
   }
   k_prep<T><<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]),
                                                      h.ldw, invdiag(h), 1.0 / h.theta, n, nullptr, 0);
-  enqueue_steps<T>(h, Slots{0, 1}, z, r, nullptr, false, 0, 0, nullptr, nullptr, s);
+  if (h.prm.form == PCHEB_FORM_NEWTON)
+    enqueue_newton<T>(h, Slots{0, 1}, z, 0, r, 0, nullptr, false, 0, 0, nullptr, s);
+  else
+    enqueue_steps<T>(h, Slots{0, 1}, z, r, nullptr, false, 0, 0, nullptr, nullptr, s);
+}
+
+// ---- Newton form of the preconditioner (Alg. 1) on B = D^-1 A_hat: the same
+// polynomial as the recurrence (Theorem 2) by the recursion
+// P_0 u = zeta_0 u, P_{j+1} u = zeta_{j+1} (2 P_j u - P_j B P_j u).
+
+// out = zeta in
+template <class T>
+__global__ void k_nt_scale(const T* in, T* out, int64_t ldw, double zeta, int64_t n, const DevState* guard,
+                           int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  in += slot * ldw;
+  out += slot * ldw;
+  using acc = typename Store<T>::acc;
+  const acc zf = acc(zeta);
+  GRID_STRIDE(i, n) Store<T>::st(out, i, zf * Store<T>::ld(in, i));
+}
+
+// out = zeta (2 t - out)
+template <class T>
+__global__ void k_nt_combine(const T* t, T* out, int64_t ldw, double zeta, int64_t n, const DevState* guard,
+                             int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  t += slot * ldw;
+  out += slot * ldw;
+  using acc = typename Store<T>::acc;
+  const acc zf = acc(zeta);
+  GRID_STRIDE(i, n) Store<T>::st(out, i, zf * (acc(2) * Store<T>::ld(t, i) - Store<T>::ld(out, i)));
+}
+
+// Top level: z = zeta (2 t - w) in float64, with (r, z) and, flexible, (z, q)
+// reduced for beta (the same partials as the last recurrence step).
+template <class T>
+__global__ void k_nt_final(const T* t, const T* w, int64_t ldw, double zeta, double* z, int64_t ldz,
+                           const double* r, int64_t ldr, const double* q, int64_t n, const DevState* guard,
+                           ReduceBuf rb, int dots, int flexible, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  t += slot * ldw;
+  w += slot * ldw;
+  z += slot * ldz;
+  r += slot * ldr;
+  if (q) q += slot * ldz;
+  using acc = typename Store<T>::acc;
+  const acc zf = acc(zeta);
+  double part[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double zi = double(zf * (acc(2) * Store<T>::ld(t, i) - Store<T>::ld(w, i)));
+    z[i] = zi;
+    if (dots) {
+      part[0] += r[i] * zi;
+      if (flexible) part[1] += zi * q[i];
+    }
+  }
+  if (dots) block_partial<2>(part, rb, slot);
+}
+
+// out = P_l in (l >= 0); level j >= 1 uses the buffers nt[2 j - 1] and nt[2 j].
+template <class T>
+static void newton_rec(Handle& h, Slots sl, int l, const T* in, T* out, const DevState* guard, hipStream_t s) {
+  const int64_t n = h.n;
+  const dim3 grid(flat_grid(n), sl.count);
+  if (l == 0) {
+    k_nt_scale<T><<<grid, kBlock, 0, s>>>(in, out, h.ldw, h.zeta[0], n, guard, sl.first);
+    return;
+  }
+  T* t1 = reinterpret_cast<T*>(h.nt[size_t(2 * l - 1)]);
+  T* t2 = reinterpret_cast<T*>(h.nt[size_t(2 * l)]);
+  newton_rec<T>(h, sl, l - 1, in, t1, guard, s);  // t1 = P_{l-1} in
+  launch_bop<T>(h, InVec<T>{t1, h.ldw}, EpiStore<T>{t2, nullptr, guard, h.ldw}, sl.first, sl.count, s);
+  newton_rec<T>(h, sl, l - 1, t2, out, guard, s);  // out = P_{l-1} B P_{l-1} in
+  k_nt_combine<T><<<grid, kBlock, 0, s>>>(t1, out, h.ldw, h.zeta[size_t(l)], n, guard, sl.first);
+}
+
+// z = P(B) s for the slots (s prepared in h.s), with the dot products of a solve when `dots`.
+template <class T>
+static void enqueue_newton(Handle& h, Slots sl, double* z, int64_t ldz, const double* r, int64_t ldr,
+                           const double* q, bool dots, int init, int flexible, DevState* guard, hipStream_t s) {
+  const int L = h.nlev;
+  const int64_t n = h.n;
+  const T* sv = reinterpret_cast<const T*>(h.s);
+  T* t1 = reinterpret_cast<T*>(h.nt[size_t(2 * L - 1)]);
+  T* t2 = reinterpret_cast<T*>(h.nt[size_t(2 * L)]);
+  T* w = reinterpret_cast<T*>(h.nt[0]);
+  newton_rec<T>(h, sl, L - 1, sv, t1, guard, s);
+  launch_bop<T>(h, InVec<T>{t1, h.ldw}, EpiStore<T>{t2, nullptr, guard, h.ldw}, sl.first, sl.count, s);
+  newton_rec<T>(h, sl, L - 1, t2, w, guard, s);
+  const uint32_t g = flat_grid(n);
+  k_nt_final<T><<<dim3(g, sl.count), kBlock, 0, s>>>(t1, w, h.ldw, h.zeta[size_t(L)], z, ldz, r, ldr, q, n, guard,
+                                                     h.rb(), dots ? 1 : 0, flexible, sl.first);
+  if (dots) k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, guard, sl.first);
 }
 
 #define PCHEB_BY_PREC(h, FN, ...)                      \
@@ -621,6 +722,11 @@ static void validate(const pcheb_operator* A, const pcheb_params* p) {
     fail(PCHEB_INVALID, "need 0 < lambda_min < lambda_max");
   if (!(p->theta_scale >= 1.0) || !std::isfinite(p->theta_scale)) fail(PCHEB_INVALID, "theta_scale must be >= 1");
   if (p->prec < PCHEB_F64 || p->prec > PCHEB_BF16) fail(PCHEB_INVALID, "unknown precision");
+  if (p->form != PCHEB_FORM_CHEBYSHEV && p->form != PCHEB_FORM_NEWTON) fail(PCHEB_INVALID, "unknown form");
+  if (p->form == PCHEB_FORM_NEWTON && ((p->k + 1) & p->k) != 0)
+    fail(PCHEB_INVALID, "the Newton form needs degree k = 2^nlev - 1");
+  if (p->form == PCHEB_FORM_NEWTON && p->prec == PCHEB_BF16)
+    fail(PCHEB_INVALID, "the Newton form needs F64 or F32 storage (its intermediates compound BF16 rounding)");
   if (A->n <= 0) fail(PCHEB_INVALID, "n must be positive");
   switch (A->kind) {
     case PCHEB_OP_CSR:
@@ -663,6 +769,22 @@ static void chebyshev_scalars(Handle& h) {
   h.rho.assign(size_t(p.k) + 1, 0.0);
   h.rho[0] = 1.0 / h.sigma;
   for (int j = 1; j <= p.k; ++j) h.rho[j] = 1.0 / (2.0 * h.sigma - h.rho[j - 1]);
+  // Newton form (Alg. 1, eq. zetaNewt) on the same shifted interval [alpha0, beta0] =
+  // [theta' - delta, theta' + delta]
+  h.nlev = 0;
+  h.zeta.clear();
+  if (p.form == PCHEB_FORM_NEWTON) {
+    while ((1 << (h.nlev + 1)) - 1 <= p.k) ++h.nlev;
+    const double a0 = h.theta - h.delta, b0 = h.theta + h.delta;
+    h.zeta.assign(size_t(h.nlev) + 1, 0.0);
+    h.zeta[0] = 2.0 / (a0 + b0);
+    if (h.nlev >= 1) {
+      const double az = a0 * h.zeta[0];
+      h.zeta[1] = 2.0 / (1.0 + 2.0 * az - az * az);
+    }
+    for (int j = 2; j <= h.nlev; ++j)
+      h.zeta[size_t(j)] = 2.0 / (1.0 + 2.0 * h.zeta[size_t(j) - 1] - h.zeta[size_t(j) - 1] * h.zeta[size_t(j) - 1]);
+  }
 }
 
 template <class T>
@@ -772,6 +894,9 @@ void ensure_workspace(Handle& h, int cap, hipStream_t stream) {
   h.s = alloc_into(ws, lw * h.elem);
   for (int i = 0; i < h.nY; ++i) h.Y[i] = alloc_into(ws, lw * h.elem);
   for (int i = h.nY; i < 4; ++i) h.Y[i] = nullptr;
+  h.nt.clear();
+  if (h.prm.form == PCHEB_FORM_NEWTON && h.nlev >= 1)
+    for (int i = 0; i < 2 * h.nlev + 1; ++i) h.nt.push_back(alloc_into(ws, lw * h.elem));
   h.r = static_cast<double*>(alloc_into(ws, lw * 8));
   h.p[0] = static_cast<double*>(alloc_into(ws, lw * 8));
   h.p[1] = static_cast<double*>(alloc_into(ws, lw * 8));
@@ -800,7 +925,10 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
   }
   if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 8 : 0);
   const int ny = (A->kind == PCHEB_OP_STENCIL7 && p->fuse_steps >= 2) ? 4 : 3;
-  const size_t per_rhs = size_t(round_up(n, 64)) * ((1 + ny) * e + 5 * 8) + sizeof(DevState) +
+  int nt = 0;  // Newton form: 2 nlev + 1 iterate vectors
+  if (p->form == PCHEB_FORM_NEWTON)
+    for (int l = 1; (1 << l) - 1 <= p->k; ++l) nt = 2 * l + 1;
+  const size_t per_rhs = size_t(round_up(n, 64)) * ((1 + ny + nt) * e + 5 * 8) + sizeof(DevState) +
                          size_t(kMaxGrid) * kMaxReduce * 8;
   b += size_t(std::max(1, nrhs)) * per_rhs + 256;
   return b;
@@ -837,7 +965,10 @@ static void enqueue_precond(Handle& h, Slots sl, int init, int flexible, StepTim
   k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(h.r, h.ldw, reinterpret_cast<T*>(h.s),
                                                             reinterpret_cast<T*>(h.Y[0]), h.ldw, invdiag(h),
                                                             1.0 / h.theta, n, h.st, sl.first);
-  enqueue_steps<T>(h, sl, h.z, h.r, h.q, true, init, flexible, h.st, timer, s);
+  if (h.prm.form == PCHEB_FORM_NEWTON)
+    enqueue_newton<T>(h, sl, h.z, h.ldw, h.r, h.ldw, h.q, true, init, flexible, h.st, s);
+  else
+    enqueue_steps<T>(h, sl, h.z, h.r, h.q, true, init, flexible, h.st, timer, s);
 }
 
 template <class T>

@@ -68,16 +68,17 @@ def test_struct_layout_matches_c(tmp_path):
             assert int(lines[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
 
 
-def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0):
+def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0, form=0):
     lib = pc.load_library()
-    p = _abi.CParams(k=k, lambda_min=lmin, lambda_max=lmax, theta_scale=s, prec=prec, fuse_steps=1)
+    p = _abi.CParams(k=k, lambda_min=lmin, lambda_max=lmax, theta_scale=s, prec=prec, fuse_steps=1, form=form)
     out = ctypes.c_void_p()
     return lib.pcheb_setup(ctypes.byref(op.c), ctypes.byref(p), None, ctypes.byref(out))
 
 
 @pytest.mark.parametrize("kw,what", [
     (dict(k=-1), "degree"), (dict(k=1001), "degree"), (dict(lmin=0.0), "lambda"), (dict(lmin=2.0), "lambda"),
-    (dict(s=0.99), "theta_scale"), (dict(prec=7), "precision"),
+    (dict(s=0.99), "theta_scale"), (dict(prec=7), "precision"), (dict(form=2), "form"),
+    (dict(k=5, form=1), "Newton"), (dict(k=6, form=1), "Newton"), (dict(k=7, form=1, prec=2), "Newton"),
 ])
 def test_setup_rejects_bad_parameters(kw, what):
     assert _setup_status(pc.Operator.stencil7(4), **kw) == 1

@@ -152,6 +152,64 @@ def test_lanczos_long_and_exhausted(pc, dims, steps):
     assert exact_lo - 1e-12 <= lo and hi <= exact_hi + 1e-12
 
 
+def newton_ref(c, r, nlev, s=1.001):
+    """D^-1/2 P_nlev(A) D^-1/2 r by the oracle's recursion of Alg. 1."""
+    a, d = oracle.jacobi_scale(oracle.csr(c.rp, c.ci, c.v))
+    dm = 1.0 / np.sqrt(d)
+    zeta = oracle.newton_zetas(c.lo, c.hi, nlev, s)
+    return dm * oracle.newton_apply(lambda v: a @ v, dm * r, zeta, nlev)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nlev", [1, 2, 3, 5])
+@pytest.mark.parametrize("name", ["st7", "h27", "csr_el", "sell_el"])
+def test_newton_apply_matches_oracle(pc, name, nlev, prec):
+    c = case(name)
+    r = W.uniform(5, c.n, -1.0, 1.0)
+    k = 2 ** nlev - 1
+    z_ref = newton_ref(c, r, nlev)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.001, prec, form="newton") as h:
+        z = torch.full((c.n,), float("nan"), dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, _t(r), z)
+        torch.cuda.synchronize()
+    zg = z.cpu().numpy()
+    assert rel_inf(zg, z_ref) <= APPLY_TOL[prec], (name, nlev, prec, rel_inf(zg, z_ref))
+
+
+@pytest.mark.parametrize("nlev", [1, 3, 5])
+@pytest.mark.parametrize("name", ["st7", "h27", "sell_h27"])
+def test_newton_equals_chebyshev_on_device(pc, name, nlev):
+    """Theorem 2 on the device: the recursion and the recurrence give the same z."""
+    c = case(name)
+    r = _t(W.uniform(6, c.n, -1.0, 1.0))
+    k = 2 ** nlev - 1
+    out = {}
+    for form in ("newton", "chebyshev"):
+        with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.001, "f64", form=form) as h:
+            z = torch.empty(c.n, dtype=torch.float64, device=DEV)
+            pc.pcheb_apply(h, r, z)
+            torch.cuda.synchronize()
+        out[form] = z.cpu().numpy()
+    assert rel_inf(out["newton"], out["chebyshev"]) <= 1e-11
+
+
+@pytest.mark.parametrize("prec,flexible", [("f64", False), ("f32", True)])
+@pytest.mark.parametrize("nlev", [2, 5])
+def test_newton_solve_matches_oracle(pc, nlev, prec, flexible):
+    c = case("st7")
+    k = 2 ** nlev - 1
+    _, b = manufactured_rhs("st7")
+    ref = oracle_solve("st7", k, 1.001, flexible)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.001, prec, form="newton") as h:
+        x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st = pc.pcg_solve(h, _t(b), x, tol=1e-8, flexible=flexible)
+    diff = np.linalg.norm(x.cpu().numpy() - ref.x_hat) / np.linalg.norm(ref.x_hat)
+    assert st["status"] == "OK" and abs(st["iters"] - ref.iters) <= 1 and diff <= 1e-6
+    assert st["relres_true"] <= TRUE_RES
+    if not flexible:
+        assert st["n_spmv"] == (k + 1) * st["iters"] and st["n_dot"] == 3 * st["iters"]
+
+
 def test_zero_rhs(pc):
     c = case("st7")
     with pc.pcheb_setup(c.operator(torch, DEV), 5, c.lo, c.hi) as h:
