@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG solves/s + P_k(A) HBM GB/s vs FP64 plain PCG; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_stencil7_256_traffic.md")
-KERNEL_SOURCES = ["operators.hpp", "epilogues.hpp", "common.hpp", "dispatch.hpp", "fused_stencil.hpp", "pcheb.hip"]
+KERNEL_SOURCES = ["common.hpp", "fused_stencil.hpp", "fused_launch.hpp"]  # the fused pass and its launch
 
 
 def log(*a):

@@ -1,0 +1,100 @@
+// Launch of the fused 7-point passes (fused_stencil.hpp): tile shape, z
+// ranges and the recurrence coefficients of the steps a pass covers.
+#pragma once
+
+#include <algorithm>
+
+#include "fused_stencil.hpp"
+#include "handle.hpp"
+
+namespace pcheb {
+
+template <class T>
+struct Coef {
+  using acc = typename Store<T>::acc;
+  acc a, b, c;
+};
+
+template <class T>
+static Coef<T> step_coef(const Handle& h, int j) {
+  using acc = typename Store<T>::acc;
+  Coef<T> c;
+  c.a = acc(2.0 * h.sigma * h.rho[j]);
+  c.b = acc(j >= 1 ? h.rho[j] * h.rho[j - 1] : 0.0);
+  c.c = acc(2.0 * h.rho[j] / h.delta);
+  return c;
+}
+
+// ---- fused passes (7-point stencil): S middle steps per launch
+
+// Tile shapes of the fused pass: 64 x TY points per block of NT threads.
+#ifndef PCHEB_FUSED_TY
+#define PCHEB_FUSED_TY 32
+#endif
+#ifndef PCHEB_FUSED_NT
+#define PCHEB_FUSED_NT 1024
+#endif
+
+template <class T, int S, int TY, int NT>
+static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T* oa, T* ob, int j,
+                         const DevState* guard, hipStream_t s) {
+  FusedCoef<typename Store<T>::acc, S> cf;
+  for (int m = 0; m < S; ++m) {
+    const Coef<T> c = step_coef<T>(h, j + m);
+    cf.a[m] = c.a;
+    cf.b[m] = c.b;
+    cf.c[m] = c.c;
+  }
+  const pcheb_operator& op = h.op;
+  const uint32_t tiles_x = uint32_t((op.nx + 63) / 64), tiles_y = uint32_t((op.ny + TY - 1) / TY);
+  const uint32_t xy = tiles_x * tiles_y;
+  // about as many tiles as the chip holds blocks at once (256 CUs, 1024 threads
+  // each in flight), each z range at least 4 S planes deep
+  const uint32_t target = 262144u / NT;
+  const int max_chunks = std::max(1, op.nz / (4 * S));
+  const int chunks = std::max(1, std::min<int>(max_chunks, int((target + xy - 1) / xy)));
+  const int zc = (op.nz + chunks - 1) / chunks;
+  const uint32_t ntiles = xy * uint32_t((op.nz + zc - 1) / zc);
+  const dim3 grid(round_grid(ntiles), sl.count);
+  const T* sv = reinterpret_cast<const T*>(h.s);
+  if constexpr (sizeof(T) < 8) {
+    // buffer-addressed form: plane byte offsets must fit the 32-bit range
+    if (int64_t(op.nx) * op.ny * int64_t(sizeof(T)) <= 0x7FFFFFF0) {
+      k_stencil7_fused_buf<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc,
+                                                             tiles_x, tiles_y, ntiles, guard, h.ldw, sl.first);
+      return;
+    }
+  }
+  // float64 (its rings do not fit the unrolled form in 128 registers) and larger planes
+  k_stencil7_fused<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
+                                                     tiles_y, ntiles, guard, h.ldw, sl.first);
+}
+
+template <class T>
+static void launch_fused_any(const Handle& h, Slots sl, int S, const T* ya, const T* yb, T* oa, T* ob, int j,
+                             const DevState* guard, hipStream_t s) {
+  constexpr int TY = PCHEB_FUSED_TY, NT = PCHEB_FUSED_NT;
+  if constexpr (sizeof(T) == 8) {
+    if (S == 2)
+      launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+    else
+      launch_fused<T, 3, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+  } else {
+    if (S == 2)
+      launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+    else if (S == 3)
+      launch_fused<T, 3, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+    else
+      launch_fused<T, 4, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+  }
+}
+
+// Steps per pass: fusion applies to the 7-point operator with four iterate
+// buffers and x-y planes of fewer than 2^31 points (32-bit in-plane offsets).
+static int effective_fuse(const Handle& h) {
+  const bool ok = h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2 && h.nY >= 4 &&
+                  int64_t(h.op.nx) * h.op.ny < (int64_t(1) << 31);
+  return ok ? h.fuse : 1;
+}
+
+}  // namespace pcheb
