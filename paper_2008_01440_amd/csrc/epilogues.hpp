@@ -114,27 +114,23 @@ struct EpiChebLast {
   }
 };
 
-// q = A p where the input functor forms p = z + beta p_old; stores p and q and
-// reduces (p, q).  The last block sets alpha = gamma / (p, q) or flags a
+// q = A p for the search direction p: stores q and reduces (p, q).  The last block sets alpha = gamma / (p, q) or flags a
 // breakdown when (p, q) <= 0.
 struct EpiDirection {
   using acc = double;
   static constexpr int NV = 1;
   static constexpr bool reduce = true;
-  double* p_new;
   double* q;
   DevState* st;
   const DevState* guard;
   int64_t ld;
   __device__ __forceinline__ void bind(int slot) {
-    p_new += slot * ld;
     q += slot * ld;
     st += slot;
     if (guard) guard += slot;
   }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ void operator()(int64_t i, double p, double ap, double (&part)[NV]) const {
-    p_new[i] = p;
     q[i] = ap;
     part[0] += p * ap;
   }

@@ -4,8 +4,8 @@
 // Each kernel evaluates m_i = (M y)_i row by row and hands
 // (i, y_i, m_i) to an epilogue functor, which does the per-row arithmetic and
 // may accumulate up to kMaxReduce partial sums for a grid reduction.  The
-// input vector is read through an input functor, so a kernel can form its
-// input on the fly (p = z + beta p_old) instead of reading a stored vector.
+// input vector is read through an input functor (a stored vector in some
+// precision, or one scaled on the fly).
 //
 // Every launch covers one or more solve slots (right-hand sides): slot =
 // slot0 + blockIdx.y.  bind(slot) points a functor at that slot's vectors
@@ -381,24 +381,6 @@ struct InVec {
   __device__ __forceinline__ void bind(int slot) { p += slot * stride; }
   __device__ __forceinline__ void prepare() {}
   __device__ __forceinline__ acc ld(int64_t i) const { return Store<T>::ld(p, i); }
-};
-
-// p = z + beta * p_old, formed where it is read (beta from the solver state).
-struct InDirection {
-  using acc = double;
-  static constexpr bool narrow = false;
-  const double* z;
-  const double* p_old;
-  const DevState* st;
-  double beta;
-  int64_t stride;
-  __device__ __forceinline__ void bind(int slot) {
-    z += slot * stride;
-    p_old += slot * stride;
-    st += slot;
-  }
-  __device__ __forceinline__ void prepare() { beta = st->beta; }
-  __device__ __forceinline__ double ld(int64_t i) const { return z[i] + beta * p_old[i]; }
 };
 
 // v scaled by D^-1/2 (for the symmetric scaled operator of the Lanczos estimator).

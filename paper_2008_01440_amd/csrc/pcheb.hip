@@ -279,6 +279,29 @@ __global__ void k_start_zero(const double* b, int64_t ldb, double* x, int64_t ld
   block_partial<2>(part, rb, slot);
 }
 
+// Search direction p = z + beta p_old, beta from the slot's state.  A pass of
+// its own: forming p inside the stencil kernel would load z and p_old for
+// every neighbour, and that kernel is bound by the issue of its loads.
+__global__ void k_direction(const double* z, const double* p_old, double* p, int64_t ldw, int64_t n,
+                            const DevState* st, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  st += slot;
+  if (st->done != kRunning) return;
+  const int64_t o = slot * ldw;
+  z += o;
+  p_old += o;
+  p += o;
+  const double beta = st->beta;
+  PAIR_STRIDE(i, n) {
+    if (i + 1 < n) {
+      const double2 zv = ld2(z, i), pv = ld2(p_old, i);
+      *reinterpret_cast<double2*>(p + i) = make_double2(zv.x + beta * pv.x, zv.y + beta * pv.y);
+    } else {
+      p[i] = z[i] + beta * p_old[i];
+    }
+  }
+}
+
 // p_old = 0 for the slots of a warm start.
 __global__ void k_zero_slots(double* p, int64_t ldw, int64_t n, int slot0) {
   p += (slot0 + int64_t(blockIdx.y)) * ldw;
@@ -901,7 +924,7 @@ static void enqueue_start(Handle& h, Slots sl, const double* b, int64_t ldb, dou
   enqueue_precond<T>(h, sl, 1, flexible, timer, s);
 }
 
-// One PCG iteration on the slots: q = A (z + beta p_old), the update with the
+// One PCG iteration on the slots: p = z + beta p_old, q = A p, the update with the
 // fused preconditioner input, and the k recurrence steps (beta formed on the device).
 template <class T>
 static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const double* b, int64_t ldb, int cur,
@@ -909,10 +932,10 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
   const int64_t n = h.n;
   DevState* st = h.st;
   double* p_new = h.p[cur ^ 1];
-  launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0, h.ldw}, EpiDirection{p_new, h.q, st, st, h.ldw}, sl.first,
-              sl.count, s);
   const uint32_t g = pair_grid(n);
   const dim3 grid(g, sl.count);
+  k_direction<<<grid, kBlock, 0, s>>>(h.z, h.p[cur], p_new, h.ldw, n, st, sl.first);
+  launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{h.q, st, st, h.ldw}, sl.first, sl.count, s);
   if (refresh) {
     k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
