@@ -112,10 +112,10 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
   }
 }
 
-// Sum over the block; the result is valid in thread 0 only.  Fixed order.
-template <int NV>
+// Sum over the block of NT threads; the result is valid in thread 0 only.  Fixed order.
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
-  __shared__ double sh[kBlock / kWave][NV > 0 ? NV : 1];
+  __shared__ double sh[NT / kWave][NV > 0 ? NV : 1];
   wave_sum<NV>(v);
   const int lane = tid % kWave, wave = tid / kWave;
   if (lane == 0) {
@@ -127,7 +127,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double s = sh[0][i];
-      for (int w = 1; w < kBlock / kWave; ++w) s += sh[w][i];
+      for (int w = 1; w < NT / kWave; ++w) s += sh[w][i];
       v[i] = s;
     }
   }
@@ -146,10 +146,10 @@ __device__ __forceinline__ size_t partial_index(int slot, uint32_t block) {
   return (size_t(slot) * kMaxGrid + block) * kMaxReduce;
 }
 
-template <int NV>
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void block_partial(double (&v)[NV], ReduceBuf rb, int slot) {
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-  block_sum<NV>(v, tid);
+  block_sum<NV, NT>(v, tid);
   if (tid == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) rb.partials[partial_index(slot, blockIdx.x) + i] = v[i];

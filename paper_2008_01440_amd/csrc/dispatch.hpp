@@ -9,17 +9,26 @@
 
 namespace pcheb {
 
-constexpr int kZChunk = 8;  // planes marched per stencil tile
+constexpr int kZChunk = 8;  // planes marched per 27-point stencil tile (64 x 4 columns)
+#ifndef PCHEB_ST7_TY
+#define PCHEB_ST7_TY 4
+#endif
+#ifndef PCHEB_ST7_ZC
+#define PCHEB_ST7_ZC 16
+#endif
+constexpr int kSt7Rows = PCHEB_ST7_TY;    // grid rows per 7-point tile (waves per block)
+constexpr int kSt7ZChunk = PCHEB_ST7_ZC;  // planes marched per 7-point tile
 
 struct StencilGrid {
   uint32_t tiles_x, tiles_y, ntiles, grid;
 };
 
-inline StencilGrid stencil_grid(const pcheb_operator& op) {
+// Tiles of 64 x rows columns by zc planes.
+inline StencilGrid stencil_grid(const pcheb_operator& op, int rows, int zc) {
   StencilGrid g;
   g.tiles_x = uint32_t((op.nx + 63) / 64);
-  g.tiles_y = uint32_t((op.ny + 3) / 4);
-  const uint32_t tz = uint32_t((op.nz + kZChunk - 1) / kZChunk);
+  g.tiles_y = uint32_t((op.ny + rows - 1) / rows);
+  const uint32_t tz = uint32_t((op.nz + zc - 1) / zc);
   g.ntiles = g.tiles_x * g.tiles_y * tz;
   g.grid = round_grid(g.ntiles);
   return g;
@@ -35,14 +44,14 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
   uint32_t grid = 0;
   switch (op.kind) {
     case PCHEB_OP_STENCIL7: {
-      const StencilGrid g = stencil_grid(op);
+      const StencilGrid g = stencil_grid(op, kSt7Rows, kSt7ZChunk);
       grid = g.grid;
-      k_stencil7<SCALED, kZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
+      k_stencil7<SCALED, kSt7Rows, kSt7ZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, kSt7Rows), 0, s>>>(
           in, epi, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_STENCIL27H: {
-      const StencilGrid g = stencil_grid(op);
+      const StencilGrid g = stencil_grid(op, 4, kZChunk);
       grid = g.grid;
       if constexpr (sizeof(acc) == 8) {
         k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(

@@ -15,6 +15,12 @@
 
 namespace pcheb {
 
+// Values an epilogue reads at its own point are loaded apart from its
+// arithmetic: pre = epi.load(i) may be issued ahead (a plane early in the
+// 7-point kernel) and is passed to epi(i, y, m, pre, part).  Epilogues that
+// read nothing use NoPre.
+struct NoPre {};
+
 // D^-1 of the unscaled operator: a stored array or a constant (7-point stencil).
 struct InvDiag {
   const double* p;
@@ -43,9 +49,15 @@ struct EpiChebStep {
     if (guard) guard += slot;
   }
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, double (&)[NV]) const {
-    acc v = a * y + c * (Store<T>::ld(s, i) - by);
-    if (!FIRST) v -= b * Store<T>::ld(yprev, i);
+  struct Pre {
+    acc s, yprev;
+  };
+  __device__ __forceinline__ Pre load(int64_t i) const {
+    return Pre{Store<T>::ld(s, i), FIRST ? acc(0) : Store<T>::ld(yprev, i)};
+  }
+  __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, const Pre& p, double (&)[NV]) const {
+    acc v = a * y + c * (p.s - by);
+    if (!FIRST) v -= b * p.yprev;
     Store<T>::st(out, i, v);
   }
   __device__ void fin(double (&)[NV]) const {}
@@ -86,14 +98,26 @@ struct EpiChebLast {
     if (guard) guard += slot;
   }
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, double (&part)[NV]) const {
-    acc v = a * y + c * (Store<T>::ld(s, i) - by);
-    if (!FIRST) v -= b * Store<T>::ld(yprev, i);
+  struct Pre {
+    acc s, yprev;
+    double r, q;
+  };
+  __device__ __forceinline__ Pre load(int64_t i) const {
+    Pre p{Store<T>::ld(s, i), FIRST ? acc(0) : Store<T>::ld(yprev, i), 0.0, 0.0};
+    if (DOTS) {
+      p.r = r[i];
+      if (flexible) p.q = q[i];
+    }
+    return p;
+  }
+  __device__ __forceinline__ void operator()(int64_t i, acc y, acc by, const Pre& p, double (&part)[NV]) const {
+    acc v = a * y + c * (p.s - by);
+    if (!FIRST) v -= b * p.yprev;
     const double zi = double(v);
     z[i] = zi;
     if (DOTS) {
-      part[0] += r[i] * zi;
-      if (flexible) part[1] += zi * q[i];
+      part[0] += p.r * zi;
+      if (flexible) part[1] += zi * p.q;
     }
   }
   __device__ void fin(double (&t)[NV]) const { finish_beta(st, t[0], t[1], init, flexible); }
@@ -114,8 +138,8 @@ struct EpiChebLast {
   }
 };
 
-// q = A p for the search direction p: stores q and reduces (p, q).  The last block sets alpha = gamma / (p, q) or flags a
-// breakdown when (p, q) <= 0.
+// q = A p for the search direction p: stores q and reduces (p, q).  The last
+// block sets alpha = gamma / (p, q) or flags a breakdown when (p, q) <= 0.
 struct EpiDirection {
   using acc = double;
   static constexpr int NV = 1;
@@ -130,7 +154,9 @@ struct EpiDirection {
     if (guard) guard += slot;
   }
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ void operator()(int64_t i, double p, double ap, double (&part)[NV]) const {
+  using Pre = NoPre;
+  __device__ __forceinline__ Pre load(int64_t) const { return {}; }
+  __device__ __forceinline__ void operator()(int64_t i, double p, double ap, const Pre&, double (&part)[NV]) const {
     q[i] = ap;
     part[0] += p * ap;
   }
@@ -156,7 +182,11 @@ struct EpiStore {
   int64_t ld;
   __device__ __forceinline__ void bind(int slot) { y += slot * ld; }
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ void operator()(int64_t i, acc, acc m, double (&)[NV]) const { Store<T>::st(y, i, m); }
+  using Pre = NoPre;
+  __device__ __forceinline__ Pre load(int64_t) const { return {}; }
+  __device__ __forceinline__ void operator()(int64_t i, acc, acc m, const Pre&, double (&)[NV]) const {
+    Store<T>::st(y, i, m);
+  }
   __device__ void fin(double (&)[NV]) const {}
 };
 
@@ -172,7 +202,13 @@ struct EpiScaledStore {
   int64_t ld;
   __device__ __forceinline__ void bind(int slot) { w += slot * ld; }
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ void operator()(int64_t i, double, double m, double (&)[NV]) const { w[i] = m * isd[i]; }
+  struct Pre {
+    double isd;
+  };
+  __device__ __forceinline__ Pre load(int64_t i) const { return Pre{isd[i]}; }
+  __device__ __forceinline__ void operator()(int64_t i, double, double m, const Pre& p, double (&)[NV]) const {
+    w[i] = m * p.isd;
+  }
   __device__ void fin(double (&)[NV]) const {}
 };
 
@@ -199,11 +235,15 @@ struct EpiResidual {
     if (guard) guard += slot;
   }
   __device__ __forceinline__ void prepare() {}
-  __device__ __forceinline__ void operator()(int64_t i, double, double ax, double (&part)[NV]) const {
-    const double bi = b[i];
+  struct Pre {
+    double b, w;
+  };
+  __device__ __forceinline__ Pre load(int64_t i) const { return Pre{b[i], invd(i)}; }
+  __device__ __forceinline__ void operator()(int64_t i, double, double ax, const Pre& p, double (&part)[NV]) const {
+    const double bi = p.b;
     const double ri = bi - ax;
     if (r) r[i] = ri;
-    const double w = invd(i);
+    const double w = p.w;
     part[0] += ri * ri * w;
     part[1] += ri * ri;
     part[2] += bi * bi * w;

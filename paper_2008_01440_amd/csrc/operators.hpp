@@ -20,8 +20,8 @@
 //   Epi: using acc; static constexpr int NV; static constexpr bool reduce;
 //        DevState* st (may be null; written by fin); const DevState* guard (may be
 //        null; the kernel does nothing once guard->done is set); __device__ void bind(int slot);
-//        __device__ void prepare();
-//        __device__ void operator()(int64_t i, acc yi, acc mi, double (&part)[NV]) const;
+//        __device__ void prepare(); struct Pre; __device__ Pre load(int64_t i) const;
+//        __device__ void operator()(int64_t i, acc yi, acc mi, const Pre&, double (&part)[NV]) const;
 //        __device__ void fin(double (&total)[NV]) const;   // thread 0 of the finalize kernel
 //
 // M is A_hat (SCALED = false) or D^-1 A_hat (SCALED = true); for CSR and
@@ -37,9 +37,9 @@ __device__ __forceinline__ bool solve_finished(const Epi& epi) {
   return epi.guard != nullptr && epi.guard->done != kRunning;
 }
 
-template <class Epi>
+template <class Epi, int NT = kBlock>
 __device__ __forceinline__ void finish_reduction(const Epi&, double (&part)[Epi::NV], ReduceBuf rb, int slot) {
-  if constexpr (Epi::reduce) block_partial<Epi::NV>(part, rb, slot);
+  if constexpr (Epi::reduce) block_partial<Epi::NV, NT>(part, rb, slot);
 }
 
 // Calls epi.fin(total) from the finalize kernel.
@@ -63,60 +63,100 @@ __device__ __forceinline__ bool bind_slot(In& in, Epi& epi, int slot) {
 
 // ------------------------------------------------------------------ 7-point stencil
 //
-// Block = 64 (x) x 4 (y) threads; a tile is 64 x 4 columns by ZC planes.  Each
-// thread marches up its column in z keeping the planes below, at and above
-// the current point in registers, so every value is fetched from memory once
-// per tile plus the x/y neighbours that the L1/L2 already hold.
-template <bool SCALED, int ZC, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_stencil7(In in, Epi epi, int nx, int ny, int nz,
-                                                     uint32_t tiles_x, uint32_t tiles_y, uint32_t ntiles,
-                                                     ReduceBuf rb, int slot0) {
+// Block = 64 (x) x TY (y) threads, one wave per grid row; a tile is 64 x TY
+// columns by ZC planes.  Each thread marches up its column in z keeping the
+// planes below, at and above its point in registers.  The tile's current
+// plane and its one-point halo are staged in LDS (two buffers, one barrier
+// per plane), so the x and y neighbours come from LDS: every input value is
+// loaded, and passed through In::ld, once per tile plane plus the halo.  The
+// halo rows y0 - 1 and y0 + TY are loaded by the first and last wave, the
+// halo columns x0 - 1 and x0 + 64 by the first 2 TY lanes of wave 1.  Values
+// outside the grid are zero.  Every thread of a block takes part in every
+// barrier; points outside the grid skip only the epilogue.
+template <bool SCALED, int TY, int ZC, class In, class Epi>
+__global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, int ny, int nz, uint32_t tiles_x,
+                                                      uint32_t tiles_y, uint32_t ntiles, ReduceBuf rb, int slot0) {
+  static_assert(TY >= 2 && 2 * TY <= 64, "halo loads need two waves and at most 64 halo columns");
   using acc = typename Epi::acc;
+  constexpr int W = 64 + 2;  // LDS row: the tile row and its two halo columns
+  __shared__ acc buf[2][TY + 2][W];
   const int slot = slot0 + int(blockIdx.y);
   if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
   const int64_t plane = int64_t(nx) * ny;
+  const int tx = int(threadIdx.x), ty = int(threadIdx.y);
+  // Loads of zero outside the grid.  Narrow (BF16) inputs are loaded from a
+  // valid address (element 0) and zeroed by a select: with a branch around
+  // each load, each conversion would wait for its load.
+  auto ld0 = [&](bool ok, int64_t j) {
+    if constexpr (In::narrow) {
+      const acc v = in.ld(ok ? j : 0);
+      return ok ? v : acc(0);
+    } else {
+      return ok ? in.ld(j) : acc(0);
+    }
+  };
+  const bool hy_on = ty == 0 || ty == TY - 1;  // this thread loads a halo row point
+  const int hy_row = ty == 0 ? 0 : TY + 1;
+  const bool hx_on = ty == 1 && tx < 2 * TY;  // this thread loads a halo column point
+  const int hx_r = tx >> 1, hx_col = (tx & 1) ? W - 1 : 0;
+  uint32_t k = 0;  // planes staged so far: buffer k & 1
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
-    const uint32_t tx = t % tiles_x;
+    const uint32_t tix = t % tiles_x;
     const uint32_t rest = t / tiles_x;
-    const uint32_t ty = rest % tiles_y;
-    const uint32_t tz = rest / tiles_y;
-    const int x = int(tx) * 64 + int(threadIdx.x);
-    const int y = int(ty) * 4 + int(threadIdx.y);
-    const int z0 = int(tz) * ZC;
-    if (x >= nx || y >= ny) continue;
+    const int x0 = int(tix) * 64;
+    const int y0 = int(rest % tiles_y) * TY;
+    const int z0 = int(rest / tiles_y) * ZC;
     const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
-    int64_t i = x + int64_t(nx) * y + plane * z0;
-    // Neighbours outside the grid read as zero.  Narrow (BF16) inputs are
-    // loaded from a valid address (the point itself) and zeroed by a select:
-    // with a branch around each load, each conversion would wait for its load.
-    auto nb = [&](bool ok, int64_t j, int64_t self) {
-      if constexpr (In::narrow) {
-        const acc v = in.ld(ok ? j : self);
-        return ok ? v : acc(0);
-      } else {
-        return ok ? in.ld(j) : acc(0);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < nx && y < ny;
+    const int64_t i0 = x + int64_t(nx) * y + plane * z0;
+    const int hy_y = ty == 0 ? y0 - 1 : y0 + TY;
+    const bool hy_ok = hy_on && x < nx && hy_y >= 0 && hy_y < ny;
+    const int64_t hy_i = x + int64_t(nx) * hy_y + plane * z0;
+    const int hx_x = (tx & 1) ? x0 + 64 : x0 - 1;
+    const bool hx_ok = hx_on && hx_x >= 0 && hx_x < nx && y0 + hx_r < ny;
+    const int64_t hx_i = hx_x + int64_t(nx) * (y0 + hx_r) + plane * z0;
+    acc below = ld0(own && z0 > 0, i0 - plane);
+    acc cur = ld0(own, i0);
+    acc above = ld0(own && z0 + 1 < nz, i0 + plane);
+    acc hy = ld0(hy_ok, hy_i), hx = ld0(hx_ok, hx_i);
+    typename Epi::Pre pre{};
+    if (own) pre = epi.load(i0);
+    for (int z = z0; z < z1; ++z, ++k) {
+      const int64_t off = plane * (z - z0);
+      // What the next plane needs is loaded one plane ahead: its point above,
+      // its halo and its epilogue inputs.
+      acc ahead = acc(0), hy_next = acc(0), hx_next = acc(0);
+      typename Epi::Pre pre_next{};
+      if (z + 1 < z1) {
+        ahead = ld0(own && z + 2 < nz, i0 + off + 2 * plane);
+        hy_next = ld0(hy_ok, hy_i + off + plane);
+        hx_next = ld0(hx_ok, hx_i + off + plane);
+        if (own) pre_next = epi.load(i0 + off + plane);
       }
-    };
-    acc below = nb(z0 > 0, i - plane, i);
-    acc centre = in.ld(i);
-    for (int z = z0; z < z1; ++z, i += plane) {
-      const acc above = nb(z + 1 < nz, i + plane, i);
-      const acc w = nb(x > 0, i - 1, i);
-      const acc e = nb(x + 1 < nx, i + 1, i);
-      const acc s = nb(y > 0, i - nx, i);
-      const acc n = nb(y + 1 < ny, i + nx, i);
-      const acc nb = ((w + e) + (s + n)) + (below + above);
-      const acc m = SCALED ? centre - nb * acc(1.0 / 6.0) : acc(6) * centre - nb;
-      epi(i, centre, m, part);
-      below = centre;
-      centre = above;
+      acc(*b)[W] = buf[k & 1];
+      b[ty + 1][tx + 1] = cur;
+      if (hy_on) b[hy_row][tx + 1] = hy;
+      if (hx_on) b[hx_r + 1][hx_col] = hx;
+      __syncthreads();
+      if (own) {
+        const acc nbs = ((b[ty + 1][tx] + b[ty + 1][tx + 2]) + (b[ty][tx + 1] + b[ty + 2][tx + 1])) + (below + above);
+        const acc m = SCALED ? cur - nbs * acc(1.0 / 6.0) : acc(6) * cur - nbs;
+        epi(i0 + off, cur, m, pre, part);
+      }
+      below = cur;
+      cur = above;
+      above = ahead;
+      hy = hy_next;
+      hx = hx_next;
+      pre = pre_next;
     }
   }
-  finish_reduction(epi, part, rb, slot);
+  finish_reduction<Epi, 64 * TY>(epi, part, rb, slot);
 }
 
 // ------------------------------------------------------------------ 27-point harmonic stencil
@@ -195,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT*
       const acc yc = yv[1][1][1];
       const acc m = SCALED ? yc - off / diag : diag * yc - off;
       const int64_t i = x + int64_t(nx) * y + plane * z;
-      epi(i, yc, m, part);
+      epi(i, yc, m, epi.load(i), part);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
@@ -282,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h_lo(In in, Epi epi, const 
       }
       const float yc = yv[1][1][1];
       const int64_t i = x + int64_t(nx) * y + plane * z;
-      epi(i, yc, yc - off * invd[i], part);
+      epi(i, yc, yc - off * invd[i], epi.load(i), part);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
@@ -325,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
     }
 #pragma unroll
     for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-    if (row < n && g == 0) epi(row, in.ld(row), sum, part);
+    if (row < n && g == 0) epi(row, in.ld(row), sum, epi.load(row), part);
   }
   finish_reduction(epi, part, rb, slot);
 }
@@ -364,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
     }
     if (pos < n) {
       const int64_t row = perm ? int64_t(perm[pos]) : pos;
-      epi(row, in.ld(row), sum, part);
+      epi(row, in.ld(row), sum, epi.load(row), part);
     }
   }
   finish_reduction(epi, part, rb, slot);
