@@ -14,6 +14,7 @@ from .nc import (
     chebyshev_scalars,
     cluster_indicator,
     csr,
+    dacg_smallest,
     hotelling_step,
     jacobi_scale,
     lanczos_extremes,
@@ -22,6 +23,7 @@ from .nc import (
     newton_apply,
     newton_zetas,
     pcg,
+    power_method,
     preconditioned_spectrum,
 )
 
@@ -35,6 +37,7 @@ __all__ = [
     "chebyshev_scalars",
     "cluster_indicator",
     "csr",
+    "dacg_smallest",
     "hotelling_step",
     "jacobi_scale",
     "lanczos_extremes",
@@ -43,5 +46,6 @@ __all__ = [
     "newton_apply",
     "newton_zetas",
     "pcg",
+    "power_method",
     "preconditioned_spectrum",
 ]

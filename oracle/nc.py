@@ -289,6 +289,65 @@ def lanczos_extremes(matvec, v0: np.ndarray, nsteps: int = 30):
     return float(ritz[0]), float(ritz[-1])
 
 
+def power_method(matvec, v0: np.ndarray, iters: int):
+    """Estimate of lambda_max by `iters` steps of the power method (Sec. 5.1).
+
+    v_0 = v0 / ||v0||; step i: w = A v_{i-1}, mu_i = (v_{i-1}, w) / (v_{i-1}, v_{i-1})
+    (the Rayleigh quotient of v_{i-1}), v_i = w / ||w||.  Returns (mu_iters, [mu_1 .. mu_iters])."""
+    v = v0 / np.linalg.norm(v0)
+    history = []
+    for _ in range(iters):
+        w = matvec(v)
+        history.append(float((v @ w) / (v @ v)))
+        v = w / np.linalg.norm(w)
+    return history[-1], history
+
+
+def dacg_smallest(matvec, v0: np.ndarray, tol: float, maxit: int):
+    """Estimate of lambda_min by the DACG method without preconditioning (Sec. 5.1,
+    after Bergamaschi, Gambolati and Pini 1997): conjugate-gradient minimisation of
+    the Rayleigh quotient q(x) = (x, A x) / (x, x).
+
+    x_0 = v0 / ||v0||.  With g_k = A x_k - q(x_k) x_k (the gradient of q up to the
+    factor 2 / (x, x)): p_0 = -g_0, p_k = -g_k + beta_k p_{k-1} with
+    beta_k = (g_k, g_k) / (g_{k-1}, g_{k-1}).  x_{k+1} minimises q on the line
+    x_k + t p_k: it is the Ritz vector of the smaller Ritz value mu of A on
+    span{x_k, p_k} (a 2 x 2 generalised eigenproblem), scaled to unit norm with a
+    non-negative x_k coefficient; A x_{k+1} follows from A x_k and A p_k, so a step
+    costs one product.  Stops when ||A x - mu x|| / (mu ||x||) <= tol or after
+    maxit steps.  Returns (mu, steps, relres)."""
+    import scipy.linalg
+
+    x = v0 / np.linalg.norm(v0)
+    ax = matvec(x)
+    xx, xax = x @ x, x @ ax
+    mu = xax / xx
+    g = ax - mu * x
+    gg = g @ g
+    relres = np.sqrt(gg) / (mu * np.sqrt(xx))
+    p = np.zeros_like(x)
+    steps = 0
+    while relres > tol and steps < maxit:
+        beta = 0.0 if steps == 0 else gg / gg_old
+        p = -g + beta * p
+        ap = matvec(p)
+        gm = np.array([[xax, x @ ap], [x @ ap, p @ ap]])
+        hm = np.array([[xx, x @ p], [x @ p, p @ p]])
+        evals, evecs = scipy.linalg.eigh(gm, hm)
+        mu = float(evals[0])
+        u = evecs[:, 0] / np.sqrt(evecs[:, 0] @ hm @ evecs[:, 0])
+        if u[0] < 0.0:
+            u = -u
+        x = u[0] * x + u[1] * p
+        ax = u[0] * ax + u[1] * ap
+        g = ax - mu * x
+        gg_old, gg = gg, g @ g
+        xx, xax = x @ x, x @ ax
+        relres = np.sqrt(gg) / (mu * np.sqrt(xx))
+        steps += 1
+    return float(mu), steps, float(relres)
+
+
 def preconditioned_spectrum(eigs: np.ndarray, lambda_min: float, lambda_max: float, k: int,
                             s: float = 1.0) -> np.ndarray:
     """Eigenvalues mu_i = lambda_i p_k(lambda_i) of p_k(A) A for A with spectrum `eigs`.

@@ -294,6 +294,55 @@ def check_table3_lap1600(ms=(7, 31, 63), band=0.10):
         assert abs(res.iters - rows[m]) <= band * rows[m], (m, res.iters, rows[m])
 
 
+def _scaled_stencil7(nx, ny, nz):
+    """matvec of D^-1/2 A D^-1/2 = A / 6 for the 7-point Laplacian, and its eigenvalue of mode (a, b, c)."""
+    rp, ci, v = W.stencil7_csr(nx, ny, nz)
+    a = O.csr(rp, ci, v)
+
+    def eig(i, j, l):
+        return 1.0 - (np.cos(np.pi * i / (nx + 1)) + np.cos(np.pi * j / (ny + 1)) + np.cos(np.pi * l / (nz + 1))) / 3.0
+
+    def mode(i, j, l):
+        x = np.sin(np.pi * i * np.arange(1, nx + 1) / (nx + 1))
+        y = np.sin(np.pi * j * np.arange(1, ny + 1) / (ny + 1))
+        z = np.sin(np.pi * l * np.arange(1, nz + 1) / (nz + 1))
+        return (z[:, None, None] * y[None, :, None] * x[None, None, :]).ravel()  # x fastest
+
+    return (lambda u: (a @ u) / 6.0), eig, mode
+
+
+def check_power_method():
+    """Power method (Sec. 5.1): from an eigenvector one step returns its eigenvalue; from a
+    random start the Rayleigh quotients never decrease (A is SPD) and reach the closed-form
+    lambda_max of the scaled 7-point operator (spectral gap 0.95 at the top of a 4 x 5 x 6 grid)."""
+    mv, eig, mode = _scaled_stencil7(4, 5, 6)
+    for m in [(4, 5, 6), (1, 1, 1), (2, 3, 1)]:
+        mu, _ = O.power_method(mv, mode(*m), 1)
+        assert abs(mu - eig(*m)) <= 1e-14, (m, mu, eig(*m))
+    mu, hist = O.power_method(mv, W.uniform(4, 120, 0.5, 1.5), 400)
+    assert np.all(np.diff(hist) >= -1e-14)
+    assert abs(mu - eig(4, 5, 6)) <= 1e-10, (mu, eig(4, 5, 6))
+
+
+def check_dacg():
+    """DACG (Sec. 5.1): at a tight tolerance it reaches the closed-form lambda_min of the scaled
+    7-point operator within a CG-like number of steps (steepest descent needs several times
+    more); at the paper's 1e-2 its estimate obeys Temple's inequality
+    mu - lambda_1 <= ||A x - mu x||^2 / (lambda_2 - mu) (unit x) and stays above lambda_1."""
+    mv, eig, _ = _scaled_stencil7(4, 5, 6)
+    mu, steps, relres = O.dacg_smallest(mv, W.uniform(5, 120, 0.5, 1.5), 1e-11, 60)
+    assert relres <= 1e-11 and abs(mu - eig(1, 1, 1)) <= 1e-12 * eig(1, 1, 1), (mu, steps, relres)
+    mv, eig, _ = _scaled_stencil7(12, 10, 8)
+    l1, l2 = eig(1, 1, 1), eig(2, 1, 1)
+    mu, steps, relres = O.dacg_smallest(mv, W.uniform(6, 960, 0.5, 1.5), 1e-2, 500)
+    assert relres <= 1e-2 and steps >= 1
+    assert l1 <= mu * (1 + 1e-13) and mu < l2
+    assert mu - l1 <= (relres * mu) ** 2 / (l2 - mu) * (1 + 1e-9), (mu, l1, l2, relres)
+    d = np.linspace(0.3, 2.0, 50)
+    mu, _, _ = O.dacg_smallest(lambda u: d * u, np.ones(50), 1e-12, 500)
+    assert abs(mu - 0.3) <= 1e-12
+
+
 ALL_FAST = [
     check_rho_closed_form,
     check_zeta_closed_form,
@@ -309,4 +358,6 @@ ALL_FAST = [
     check_counting_identities,
     check_lanczos_exact_small,
     check_indefinite_breakdown,
+    check_power_method,
+    check_dacg,
 ]

@@ -57,6 +57,14 @@ def test_lanczos_exact_when_space_spanned():
     pins.check_lanczos_exact_small()
 
 
+def test_power_method_closed_form():
+    pins.check_power_method()
+
+
+def test_dacg_closed_form_and_temple_bound():
+    pins.check_dacg()
+
+
 def test_underestimated_bound_breaks_down():
     pins.check_indefinite_breakdown()
 

@@ -58,6 +58,16 @@ MUTANTS = [
     ("cluster_indicator", "mu / mu.min() < 1.1", "mu / mu.min() < 1.01", "cluster threshold"),
     ("lanczos_extremes", "w = w - v[:j + 1].T @ (v[:j + 1] @ w)", "w = w - v[:j].T @ (v[:j] @ w)",
      "reorthogonalisation skips the current vector"),
+    ("power_method", "history.append(float((v @ w) / (v @ v)))", "history.append(float((w @ w) / (v @ v)))",
+     "power method returns lambda^2"),
+    ("power_method", "return history[-1], history", "return history[0], history", "power method first estimate"),
+    ("dacg_smallest", "        g = ax - mu * x", "        g = ax + mu * x", "DACG gradient sign"),
+    ("dacg_smallest", "beta = 0.0 if steps == 0 else gg / gg_old", "beta = 0.0",
+     "DACG without conjugation (steepest descent)"),
+    ("dacg_smallest", "beta = 0.0 if steps == 0 else gg / gg_old", "beta = 0.0 if steps == 0 else gg_old / gg",
+     "DACG beta inverted"),
+    ("dacg_smallest", "mu = float(evals[0])", "mu = float(evals[1])", "DACG larger Ritz value"),
+    ("dacg_smallest", "u = evecs[:, 0] / np.sqrt", "u = evecs[:, 1] / np.sqrt", "DACG larger Ritz vector"),
 ]
 
 
