@@ -94,6 +94,10 @@ def main():
                     help="comma-separated subset of c1,c2,c3,c4: per-configuration measurements, one JSON line each")
     ap.add_argument("--paper-scale", default="",
                     help="comma-separated nx of lap3d(nx) solves at the paper's sizes (e.g. 512,1024)")
+    ap.add_argument("--paper-bounds", default="exact", choices=["exact", "pdacg"],
+                    help="bounds of the --paper-scale solves: closed form, or the paper's power method + DACG")
+    ap.add_argument("--bounds", action="store_true",
+                    help="compare bound estimators (Lanczos, power method + DACG, exact) on the flagship problem")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -116,7 +120,10 @@ def main():
         return
     if args.paper_scale:
         for nx in (int(v) for v in args.paper_scale.split(",")):
-            run_paper_scale(nx, torch, pc, W, dev)
+            run_paper_scale(nx, torch, pc, W, dev, args.paper_bounds)
+        return
+    if args.bounds:
+        run_bounds(args, torch, pc, W, dev)
         return
     configs = [c for c in args.configs.split(",") if c]
     for c in configs:
@@ -435,16 +442,41 @@ def run_c4(torch, pc, W, dev):
                       "lambda_max": hi, "rows": rows}), flush=True)
 
 
-def run_paper_scale(nx, torch, pc, W, dev):
+PD_POWER_STEPS = 30  # "few" power steps for lambda_max
+PD_DACG_TOL = 1e-2   # DACG tolerance of Sec. 5.1
+
+
+def paper_estimate(pc, torch, op, n, dev):
+    """The paper's bound estimates (Sec. 5.1) from a SplitMix64 U[0.5, 1.5) start vector (seed 7)."""
+    v0 = torch.empty(n, dtype=torch.float64, device=dev)
+    pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = pc.pcheb_estimate_bounds_pdacg(op, v0, PD_POWER_STEPS, PD_DACG_TOL, 1000000)
+    r["seconds"] = time.perf_counter() - t0
+    del v0
+    torch.cuda.empty_cache()
+    return r
+
+
+def run_paper_scale(nx, torch, pc, W, dev, bounds="exact"):
     """lap3d(nx): the 7-point Poisson problem of the paper's large runs, (nx - 1)^3 unknowns,
-    matrix-free, s = 1.001, tol 1e-8, x0 = 0, closed-form bounds (a Lanczos basis does not fit
-    at 1023^3), degrees k = 2^nlev - 1 for nlev in {5, 2, 0}.  Right-hand sides: b = A_hat 1
+    matrix-free, s = 1.001, tol 1e-8, x0 = 0, degrees k = 2^nlev - 1 for nlev in {5, 2, 0}.
+    Bounds: closed form (a Lanczos basis does not fit at 1023^3), or the paper's estimators
+    (30 power steps, DACG to 1e-2; lambda_max widened by 1.01).  Right-hand sides: b = A_hat 1
     (x* = ones) and b ~ U[0, 1] (SplitMix64 seed 0), both formed on the device.  One solve per
     case (the first includes the capture of its iteration graph); prints a JSON line per case."""
     N = nx - 1
     n = N ** 3
     op = pc.Operator.stencil7(N)
     lo, hi = W.stencil7_bounds(N)
+    est = None
+    if bounds == "pdacg":
+        est = paper_estimate(pc, torch, op, n, dev)
+        log(f"lap3d({nx}): power({PD_POWER_STEPS}) + DACG({PD_DACG_TOL}) bounds [{est['lambda_min']:.6g}, "
+            f"{est['lambda_max']:.6g}] (exact [{lo:.6g}, {hi:.6g}]), {est['dacg_steps']} DACG steps, "
+            f"{est['seconds']:.2f} s")
+        lo, hi = est["lambda_min"], 1.01 * est["lambda_max"]
     b = torch.empty(n, dtype=torch.float64, device=dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     cases = [(5, "f32", 4, True), (5, "f64", 3, False), (2, "f32", 1, True), (0, "f64", 1, False)]
@@ -470,12 +502,73 @@ def run_paper_scale(nx, torch, pc, W, dev):
             solve_s = time.perf_counter() - t0
             pc.pcheb_destroy(h)
             print(json.dumps({"mode": "paper_scale", "problem": f"lap3d({nx})", "n": n, "rhs": rhs, "nlev": nlev,
+                              "bounds": bounds, "lambda_min": lo, "lambda_max": hi,
+                              "estimate_s": round(est["seconds"], 3) if est else None,
+                              "dacg_steps": est["dacg_steps"] if est else None,
                               "k": k, "prec": prec, "steps_per_pass": fuse, "flexible": flexible,
                               "iters": st["iters"], "status": st["status"], "solve_s": round(solve_s, 3),
                               "setup_s": round(setup_s, 3), "relres_true": st["relres_true"],
                               "n_spmv": st["n_spmv"], "n_dot": st["n_dot"]}), flush=True)
     del b, x
     torch.cuda.empty_cache()
+
+
+def run_bounds(args, torch, pc, W, dev):
+    """Bound estimators on the flagship problem (n^3 7-point Poisson, k, F32, four steps per pass):
+    Lanczos(30); the paper's power method (30, 300, 1000 steps) for lambda_max and DACG (1e-2)
+    for lambda_min; DACG with Lanczos' lambda_max; the closed-form spectrum.  Estimated upper
+    bounds are widened by 1.01, and the paper's 30-step estimate is also used as is (s = 1.001
+    only).  For each: the estimate, its time, and the flexible NC-PCG solve with those bounds
+    (b = A x*, tol 1e-8, at most 5000 iterations)."""
+    n1 = args.n
+    n = n1 ** 3
+    op = pc.Operator.stencil7(n1)
+    rp, ci, v = W.stencil7_csr(n1)
+    xstar = W.uniform(0, n, -1.0, 1.0)
+    bt = torch.from_numpy(W.rhs_from_solution(rp, ci, v, xstar)).to(dev)
+    del rp, ci, v
+    exact_lo, exact_hi = W.stencil7_bounds(n1)
+    v0 = torch.empty(n, dtype=torch.float64, device=dev)
+    pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l_lo, l_hi = pc.pcheb_estimate_bounds(op, v0, 30)
+    lanczos_s = time.perf_counter() - t0
+    power = {}
+    for steps in (30, 300, 1000):
+        t0 = time.perf_counter()
+        power[steps] = (pc.pcheb_estimate_bounds_pdacg(op, v0, steps, 1.0, 0)["lambda_max"], time.perf_counter() - t0)
+    del v0
+    est = paper_estimate(pc, torch, op, n, dev)  # 30 power steps + DACG
+    d_lo, d_s = est["lambda_min"], est["seconds"] - power[30][1]
+    log(f"DACG({PD_DACG_TOL}): lambda_min {d_lo:.6g} in {est['dacg_steps']} steps, {d_s:.3f}s; power: "
+        + ", ".join(f"{k} steps {v[0]:.6g} ({v[1]:.3f}s)" for k, v in power.items()))
+    rows = []
+    cases = [("lanczos30_x1.01", l_lo, 1.01 * l_hi, lanczos_s),
+             ("power30_dacg_as_printed", d_lo, power[30][0], power[30][1] + d_s)]
+    cases += [(f"power{k}_dacg_x1.01", d_lo, 1.01 * power[k][0], power[k][1] + d_s) for k in (30, 300, 1000)]
+    cases += [("dacg_lanczos30_x1.01", d_lo, 1.01 * l_hi, lanczos_s + d_s), ("exact", exact_lo, exact_hi, 0.0)]
+    for name, lo, hi, secs in cases:
+        h = pc.pcheb_setup(op, args.k, lo, hi, 1.001, args.prec, fuse_steps=args.fuse)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        pc.pcg_solve(h, bt, x, tol=1e-8, maxit=5000, flexible=True, check=False)  # warm-up (graph capture)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = pc.pcg_solve(h, bt, x, tol=1e-8, maxit=5000, flexible=True, check=False)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+        pc.pcheb_destroy(h)
+        rows.append({"bounds": name, "lambda_min": lo, "lambda_max": hi, "estimate_s": round(secs, 4),
+                     "iters": st["iters"], "status": st["status"], "solve_s": round(solve_s, 4),
+                     "relres_true": st["relres_true"]})
+        log(f"  {name:24s} [{lo:.6g}, {hi:.6g}] est {secs:.3f}s  iters {st['iters']}  {st['status']}  "
+            f"solve {solve_s:.3f}s")
+    print(json.dumps({"mode": "bounds", "workload": f"3-D 7-point Poisson {n1}^3, k={args.k}, {args.prec}, "
+                      f"S={args.fuse}, b = A x*, tol 1e-8", "exact": [exact_lo, exact_hi],
+                      "dacg_steps": est["dacg_steps"], "dacg_relres": est["dacg_relres"], "dacg_s": round(d_s, 4),
+                      "power": {str(k): {"lambda_max": v[0], "seconds": round(v[1], 4)} for k, v in power.items()},
+                      "rows": rows}), flush=True)
 
 
 def run_serve(args, rate, torch, pc, W, dev):

@@ -221,6 +221,30 @@ size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int
 pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
                                    double* lambda_min, double* lambda_max, hipStream_t stream);
 
+/*
+ * The paper's bound estimates (Sec. 5.1) for the Jacobi-scaled operator
+ * A = D^-1/2 A_hat D^-1/2, both started from v0 (device float64[n], need not
+ * be normalised; it is only read):
+ *  - lambda_max: power_iters steps of the power method, v <- A v / ||A v||;
+ *    the Rayleigh quotient of the last iterate (a lower estimate of
+ *    lambda_max: callers widen it before pcheb_setup);
+ *  - lambda_min: the DACG method without preconditioning (conjugate-gradient
+ *    minimisation of the Rayleigh quotient, Bergamaschi, Gambolati and Pini
+ *    1997) until ||A x - mu x|| / (mu ||x||) <= dacg_tol (the paper uses
+ *    1e-2) or dacg_maxit steps; mu is an upper estimate of lambda_min.
+ * Writes *lambda_min, *lambda_max and, if not NULL, *dacg_steps and
+ * *dacg_relres (host); synchronises `stream` before returning.  Allocates 6
+ * vectors of workspace for the duration of the call.  One operator product
+ * per power step and per DACG step.
+ * Errors: INVALID (bad arguments, a zero or non-finite v0), NOT_SPD,
+ * BREAKDOWN (non-finite values, or a direction parallel to the iterate),
+ * OOM, HIP.  Reaching dacg_maxit is not an error: *dacg_relres tells.
+ */
+pcheb_status pcheb_estimate_bounds_pdacg(const pcheb_operator* A, const double* v0, int32_t power_iters,
+                                         double dacg_tol, int32_t dacg_maxit, double* lambda_min,
+                                         double* lambda_max, int32_t* dacg_steps, double* dacg_relres,
+                                         hipStream_t stream);
+
 /* Seeded uniform vector (workload generation, not part of the method):
  * v[i] = lo + (hi - lo) * U_i for i < n, where U_i is element i of the
  * counter-based SplitMix64 stream of `seed` (Steele, Lea & Flood, OOPSLA

@@ -25,6 +25,7 @@ from ._abi import (
     pcheb_apply,
     pcheb_destroy,
     pcheb_estimate_bounds,
+    pcheb_estimate_bounds_pdacg,
     pcheb_fill_uniform,
     pcheb_footprint_bytes,
     pcheb_last_error,
@@ -49,6 +50,7 @@ __all__ = [
     "pcheb_apply",
     "pcheb_destroy",
     "pcheb_estimate_bounds",
+    "pcheb_estimate_bounds_pdacg",
     "pcheb_fill_uniform",
     "pcheb_footprint_bytes",
     "pcheb_last_error",

@@ -137,6 +137,8 @@ def load_library():
     lib.pcheb_footprint_bytes.restype = ctypes.c_size_t
     lib.pcheb_estimate_bounds.argtypes = [ctypes.POINTER(COperator), vp, i32, ctypes.POINTER(f64),
                                           ctypes.POINTER(f64), vp]
+    lib.pcheb_estimate_bounds_pdacg.argtypes = [ctypes.POINTER(COperator), vp, i32, f64, i32, ctypes.POINTER(f64),
+                                                ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(f64), vp]
     lib.pcheb_fill_uniform.argtypes = [vp, i64, ctypes.c_uint64, f64, f64, vp]
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.pserve_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(vp)]
@@ -147,7 +149,7 @@ def load_library():
     lib.pserve_get_stats.argtypes = [vp, ctypes.POINTER(CServeStats)]
     lib.pserve_destroy.argtypes = [vp]
     for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
-                 "pcheb_estimate_bounds", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
+                 "pcheb_estimate_bounds", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
                  "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -323,6 +325,20 @@ def pcheb_estimate_bounds(op: Operator, v0, nsteps: int = 30, stream=None):
     _check(load_library().pcheb_estimate_bounds(ctypes.byref(op.c), _dptr(v0, "float64"), nsteps,
                                                 ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
     return lo.value, hi.value
+
+
+def pcheb_estimate_bounds_pdacg(op: Operator, v0, power_iters: int = 30, dacg_tol: float = 1e-2,
+                                dacg_maxit: int = 100000, stream=None) -> dict:
+    """The paper's bound estimates (Sec. 5.1): lambda_max from `power_iters` power-method steps,
+    lambda_min from DACG without preconditioning, stopped at relative eigen-residual `dacg_tol`.
+    Returns {"lambda_min", "lambda_max", "dacg_steps", "dacg_relres"}."""
+    lo, hi, rr = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    steps = ctypes.c_int32()
+    _check(load_library().pcheb_estimate_bounds_pdacg(ctypes.byref(op.c), _dptr(v0, "float64"), int(power_iters),
+                                                      float(dacg_tol), int(dacg_maxit), ctypes.byref(lo),
+                                                      ctypes.byref(hi), ctypes.byref(steps), ctypes.byref(rr),
+                                                      _stream(stream)))
+    return {"lambda_min": lo.value, "lambda_max": hi.value, "dacg_steps": steps.value, "dacg_relres": rr.value}
 
 
 def pcheb_fill_uniform(v, seed: int, lo: float = 0.0, hi: float = 1.0, stream=None):

@@ -28,7 +28,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
-                 "pcheb_footprint_bytes", "pcheb_estimate_bounds", "pserve_create", "pserve_submit", "pserve_poll",
+                 "pcheb_footprint_bytes", "pcheb_estimate_bounds", "pcheb_estimate_bounds_pdacg", "pserve_create",
+                 "pserve_submit", "pserve_poll",
                  "pserve_wait", "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         assert name in fns
 
@@ -108,6 +109,23 @@ def test_null_arguments():
     assert lib.pcheb_destroy(None) == 0
     lo, hi = ctypes.c_double(), ctypes.c_double()
     assert lib.pcheb_estimate_bounds(None, None, 30, ctypes.byref(lo), ctypes.byref(hi), None) == 1
+    assert lib.pcheb_estimate_bounds_pdacg(None, None, 30, 1e-2, 100, ctypes.byref(lo), ctypes.byref(hi), None, None,
+                                           None) == 1
+
+
+def test_pdacg_argument_checks():
+    """Argument errors are reported before any device work (the operator is never touched)."""
+    lib = pc.load_library()
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    op = pc.Operator.stencil7(4)
+    args = lambda it, tol, mx, a=ctypes.byref(lo), b=ctypes.byref(hi): lib.pcheb_estimate_bounds_pdacg(
+        ctypes.byref(op.c), None, it, tol, mx, a, b, None, None, None)
+    assert args(0, 1e-2, 10) == 1 and "power_iters" in pc.pcheb_last_error()
+    assert args(5, -1.0, 10) == 1 and "dacg_tol" in pc.pcheb_last_error()
+    assert args(5, float("nan"), 10) == 1 and "dacg_tol" in pc.pcheb_last_error()
+    assert args(5, 1e-2, -1) == 1 and "dacg_maxit" in pc.pcheb_last_error()
+    assert args(5, 1e-2, 10, None) == 1 and "null" in pc.pcheb_last_error()
+    assert args(5, 1e-2, 10) == 1 and "null" in pc.pcheb_last_error()  # v0 is NULL
 
 
 def test_server_argument_checks():

@@ -152,6 +152,62 @@ def test_lanczos_long_and_exhausted(pc, dims, steps):
     assert exact_lo - 1e-12 <= lo and hi <= exact_hi + 1e-12
 
 
+@pytest.mark.parametrize("name", ["st7", "h27", "csr_el", "sell_h27"])
+def test_power_dacg_match_oracle(pc, name):
+    """The paper's estimators (Sec. 5.1) from the same start vector: 25 power steps, and
+    DACG to the paper's 1e-2 (same step count, same estimate) and for exactly 40 steps."""
+    c = case(name)
+    v0 = W.uniform(8, c.n, 0.5, 1.5)
+    a, _ = oracle.jacobi_scale(oracle.csr(c.rp, c.ci, c.v))
+    mv = lambda x: a @ x
+    hi_ref, _ = oracle.power_method(mv, v0, 25)
+    lo_ref, steps_ref, rr_ref = oracle.dacg_smallest(mv, v0, 1e-2, 5000)
+    op = c.operator(torch, DEV)
+    r = pc.pcheb_estimate_bounds_pdacg(op, _t(v0), 25, 1e-2, 5000)
+    assert abs(r["lambda_max"] - hi_ref) <= 1e-12 * hi_ref, (r, hi_ref)
+    assert r["dacg_steps"] == steps_ref and r["dacg_relres"] <= 1e-2, (r, steps_ref, rr_ref)
+    assert abs(r["lambda_min"] - lo_ref) <= 1e-10 * lo_ref and abs(r["dacg_relres"] - rr_ref) <= 1e-6 * rr_ref
+    # The Rayleigh quotient is second-order in the iterate's rounding differences, the
+    # residual first-order: like CG iterates, DACG iterates drift apart under different
+    # summation orders (observed 7e-7 relative in the residual after 40 steps, 1e-16 in mu).
+    lo40, steps40, rr40 = oracle.dacg_smallest(mv, v0, 0.0, 40)
+    r = pc.pcheb_estimate_bounds_pdacg(op, _t(v0), 1, 0.0, 40)
+    assert r["dacg_steps"] == steps40 == 40
+    assert abs(r["lambda_min"] - lo40) <= 1e-10 * lo40 and abs(r["dacg_relres"] - rr40) <= 1e-4 * rr40, (r, lo40, rr40)
+
+
+def test_power_dacg_closed_forms(pc):
+    """Properties at a size the oracle is not run at (48 x 40 x 36 scaled 7-point operator,
+    closed-form spectrum): one power step from the top eigenvector returns lambda_max; DACG at
+    the paper's 1e-2 stops with the residual below it, above lambda_1, and within Temple's
+    bound (relres mu)^2 / (lambda_2 - mu) of it; power estimates stay below lambda_max."""
+    nx, ny, nz = 48, 40, 36
+    op = pc.Operator.stencil7(nx, ny, nz)
+
+    def eig(i, j, l):
+        return 1.0 - (np.cos(np.pi * i / (nx + 1)) + np.cos(np.pi * j / (ny + 1)) + np.cos(np.pi * l / (nz + 1))) / 3.0
+
+    sx = np.sin(np.pi * nx * np.arange(1, nx + 1) / (nx + 1))
+    sy = np.sin(np.pi * ny * np.arange(1, ny + 1) / (ny + 1))
+    sz = np.sin(np.pi * nz * np.arange(1, nz + 1) / (nz + 1))
+    top = (sz[:, None, None] * sy[None, :, None] * sx[None, None, :]).ravel()
+    r = pc.pcheb_estimate_bounds_pdacg(op, _t(top), 1, 1.0, 0)
+    assert abs(r["lambda_max"] - eig(nx, ny, nz)) <= 1e-13 and r["dacg_steps"] == 0
+    v0 = W.uniform(9, nx * ny * nz, 0.5, 1.5)
+    r = pc.pcheb_estimate_bounds_pdacg(op, _t(v0), 30, 1e-2, 100000)
+    l1, l2 = eig(1, 1, 1), eig(2, 1, 1)
+    mu, rr = r["lambda_min"], r["dacg_relres"]
+    assert rr <= 1e-2 and l1 <= mu * (1 + 1e-12) and mu < l2, r
+    assert mu - l1 <= (rr * mu) ** 2 / (l2 - mu) * (1 + 1e-6), (r, l1, l2)
+    assert r["lambda_max"] <= eig(nx, ny, nz) * (1 + 1e-14)
+
+
+def test_power_dacg_rejects_zero_start(pc):
+    op = pc.Operator.stencil7(8)
+    with pytest.raises(RuntimeError, match="nonzero"):
+        pc.pcheb_estimate_bounds_pdacg(op, torch.zeros(512, dtype=torch.float64, device=DEV), 5, 1e-2, 10)
+
+
 def newton_ref(c, r, nlev, s=1.001):
     """D^-1/2 P_nlev(A) D^-1/2 r by the oracle's recursion of Alg. 1."""
     a, d = oracle.jacobi_scale(oracle.csr(c.rp, c.ci, c.v))
