@@ -442,7 +442,7 @@ def run_c4(torch, pc, W, dev):
                       "lambda_max": hi, "rows": rows}), flush=True)
 
 
-PD_POWER_STEPS = 30  # "few" power steps for lambda_max
+PD_POWER_STEPS = 300  # power steps for lambda_max (30 land 2.6% low on 256^3, 300 within 0.3%)
 PD_DACG_TOL = 1e-2   # DACG tolerance of Sec. 5.1
 
 
@@ -463,7 +463,7 @@ def run_paper_scale(nx, torch, pc, W, dev, bounds="exact"):
     """lap3d(nx): the 7-point Poisson problem of the paper's large runs, (nx - 1)^3 unknowns,
     matrix-free, s = 1.001, tol 1e-8, x0 = 0, degrees k = 2^nlev - 1 for nlev in {5, 2, 0}.
     Bounds: closed form (a Lanczos basis does not fit at 1023^3), or the paper's estimators
-    (30 power steps, DACG to 1e-2; lambda_max widened by 1.01).  Right-hand sides: b = A_hat 1
+    (300 power steps, DACG to 1e-2; lambda_max widened by 1.01).  Right-hand sides: b = A_hat 1
     (x* = ones) and b ~ U[0, 1] (SplitMix64 seed 0), both formed on the device.  One solve per
     case (the first includes the capture of its iteration graph); prints a JSON line per case."""
     N = nx - 1
@@ -497,7 +497,7 @@ def run_paper_scale(nx, torch, pc, W, dev, bounds="exact"):
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st = pc.pcg_solve(h, b, x, tol=1e-8, maxit=20000, flexible=flexible)
+            st = pc.pcg_solve(h, b, x, tol=1e-8, maxit=20000, flexible=flexible, check=False)
             torch.cuda.synchronize()
             solve_s = time.perf_counter() - t0
             pc.pcheb_destroy(h)
@@ -539,8 +539,8 @@ def run_bounds(args, torch, pc, W, dev):
         t0 = time.perf_counter()
         power[steps] = (pc.pcheb_estimate_bounds_pdacg(op, v0, steps, 1.0, 0)["lambda_max"], time.perf_counter() - t0)
     del v0
-    est = paper_estimate(pc, torch, op, n, dev)  # 30 power steps + DACG
-    d_lo, d_s = est["lambda_min"], est["seconds"] - power[30][1]
+    est = paper_estimate(pc, torch, op, n, dev)  # PD_POWER_STEPS power steps + DACG
+    d_lo, d_s = est["lambda_min"], est["seconds"] - power[PD_POWER_STEPS][1]
     log(f"DACG({PD_DACG_TOL}): lambda_min {d_lo:.6g} in {est['dacg_steps']} steps, {d_s:.3f}s; power: "
         + ", ".join(f"{k} steps {v[0]:.6g} ({v[1]:.3f}s)" for k, v in power.items()))
     rows = []
