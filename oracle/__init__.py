@@ -10,6 +10,7 @@ from .nc import (
     NCResult,
     NotSPD,
     PCGResult,
+    block_jacobi_factor,
     chebyshev_apply,
     chebyshev_scalars,
     cluster_indicator,
@@ -19,12 +20,15 @@ from .nc import (
     jacobi_scale,
     lanczos_extremes,
     nc_apply_unscaled,
+    nc_apply_second_level,
     nc_pcg,
+    nc_pcg_second_level,
     newton_apply,
     newton_zetas,
     pcg,
     power_method,
     preconditioned_spectrum,
+    second_level_operator,
 )
 
 __all__ = [
@@ -33,6 +37,7 @@ __all__ = [
     "NCResult",
     "NotSPD",
     "PCGResult",
+    "block_jacobi_factor",
     "chebyshev_apply",
     "chebyshev_scalars",
     "cluster_indicator",
@@ -42,10 +47,13 @@ __all__ = [
     "jacobi_scale",
     "lanczos_extremes",
     "nc_apply_unscaled",
+    "nc_apply_second_level",
     "nc_pcg",
+    "nc_pcg_second_level",
     "newton_apply",
     "newton_zetas",
     "pcg",
     "power_method",
     "preconditioned_spectrum",
+    "second_level_operator",
 ]

@@ -261,6 +261,66 @@ def nc_apply_unscaled(rowptr, colind, values, r_hat, lambda_min, lambda_max, k, 
     return dm * chebyshev_apply(lambda v: a @ v, dm * r_hat, c, k)
 
 
+def block_jacobi_factor(a: sp.csr_matrix, bs: int = 3) -> sp.csr_matrix:
+    """A first-level preconditioner in factored form, P0 = W W^T (the closing remark of Sec. 6):
+    block Jacobi with the bs x bs diagonal blocks A_II (for 3-D elasticity, the three displacement
+    components of one node).  A_II = L_I L_I^T (Cholesky) and W = blockdiag(L_I^-T), so that
+    W W^T = blockdiag(A_II)^-1 and W^T A W has identity diagonal blocks.  Raises NotSPD if a
+    block is not positive definite."""
+    n = a.shape[0]
+    if n % bs:
+        raise ValueError("n must be a multiple of the block size")
+    factors = []
+    for i in range(0, n, bs):
+        try:
+            l = np.linalg.cholesky(a[i:i + bs, i:i + bs].toarray())
+        except np.linalg.LinAlgError as exc:
+            raise NotSPD("a diagonal block is not positive definite") from exc
+        factors.append(np.linalg.inv(l).T)
+    return sp.block_diag(factors, format="csr")
+
+
+def second_level_operator(rowptr, colind, values, bs: int = 3):
+    """(A, d, W, C): the Jacobi-scaled A = D^-1/2 A_hat D^-1/2, d = diag(A_hat), the block
+    Jacobi factor W of A and C = W^T A W, the matrix the second-level polynomial acts on."""
+    a, d = jacobi_scale(csr(rowptr, colind, values))
+    w = block_jacobi_factor(a, bs)
+    return a, d, w, (w.T @ a @ w).tocsr()
+
+
+def nc_apply_second_level(rowptr, colind, values, r_hat, lambda_min, lambda_max, k, s=1.001, bs=3):
+    """The second-level NC preconditioner on the unscaled system:
+    D^-1/2 W p_k(W^T A W) W^T D^-1/2 r_hat, with [lambda_min, lambda_max] bounding the spectrum of
+    C = W^T A W (Sec. 6, closing remark; k = 0 gives block Jacobi, W W^T / theta')."""
+    _, d, w, cm = second_level_operator(rowptr, colind, values, bs)
+    dm = 1.0 / np.sqrt(d)
+    c = chebyshev_scalars(lambda_min, lambda_max, k, s)
+    return dm * (w @ chebyshev_apply(lambda v: cm @ v, w.T @ (dm * r_hat), c, k))
+
+
+def nc_pcg_second_level(rowptr, colind, values, b_hat, lambda_min, lambda_max, k, s=1.001, tol=1e-8,
+                        maxit=100000, flexible=False, bs=3) -> "NCResult":
+    """PCG on the Jacobi-scaled system, as nc_pcg, preconditioned by W p_k(W^T A W) W^T, the
+    paper's second-level construction on the block Jacobi factor P0 = W W^T of A."""
+    a_hat = csr(rowptr, colind, values)
+    a, d = jacobi_scale(a_hat)
+    w = block_jacobi_factor(a, bs)
+    dm = 1.0 / np.sqrt(d)
+    b = dm * b_hat
+    op = CountingOperator(a)
+    c = chebyshev_scalars(lambda_min, lambda_max, k, s)
+    res = pcg(op, b, lambda r: w @ chebyshev_apply(lambda v: w.T @ op(w @ v), w.T @ r, c, k), tol, maxit,
+              flexible)
+    x_hat = dm * res.x
+    rt = b - a @ res.x
+    rt_hat = b_hat - a_hat @ x_hat
+    bn, bhn = np.linalg.norm(b), np.linalg.norm(b_hat)
+    return NCResult(x_hat, res.iters, res.converged, res.breakdown, res.relres,
+                    float(np.linalg.norm(rt) / bn) if bn > 0 else 0.0,
+                    float(np.linalg.norm(rt_hat) / bhn) if bhn > 0 else 0.0,
+                    op.count, res.n_dot, res.history)
+
+
 def lanczos_extremes(matvec, v0: np.ndarray, nsteps: int = 30):
     """Extreme Ritz values of `nsteps` Lanczos steps with full reorthogonalisation.
 

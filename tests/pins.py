@@ -343,6 +343,52 @@ def check_dacg():
     assert abs(mu - 0.3) <= 1e-12
 
 
+def check_second_level():
+    """The second-level construction (Sec. 6, closing remark) on the block Jacobi factor:
+    W^T A W has identity 3 x 3 diagonal blocks and W W^T inverts the diagonal blocks of A;
+    W p_k(W^T A W) W^T r equals p_k(B^-1 A) B^-1 r (B = blockdiag(A_II)), the form a
+    recurrence on B^-1 A with input B^-1 r computes; with 1 x 1 blocks the construction is the
+    plain NC preconditioner; and its PCG solves the system (dense solve)."""
+    rp, ci, v = W.elasticity_q1_csr(3, seed=5)
+    a, d, w, cm = O.second_level_operator(rp, ci, v)
+    n = a.shape[0]
+    cd = cm.toarray()
+    for i in range(0, n, 3):
+        assert np.abs(cd[i:i + 3, i:i + 3] - np.eye(3)).max() <= 1e-13
+    ww = (w @ w.T).toarray()
+    ad = a.toarray()
+    for i in range(0, n, 3):
+        assert np.abs(ww[i:i + 3, i:i + 3] @ ad[i:i + 3, i:i + 3] - np.eye(3)).max() <= 1e-12
+    eig = np.linalg.eigvalsh(cd)
+    lo, hi = eig[0], eig[-1]
+    r = W.uniform(11, n, -1.0, 1.0)
+    dm = 1.0 / np.sqrt(d)
+    binv = np.zeros((n, n))
+    for i in range(0, n, 3):
+        binv[i:i + 3, i:i + 3] = np.linalg.inv(ad[i:i + 3, i:i + 3])
+    c = O.chebyshev_scalars(lo, hi, 7, 1.001)
+    ref = dm * O.chebyshev_apply(lambda u: binv @ (ad @ u), binv @ (dm * r), c, 7)
+    z = O.nc_apply_second_level(rp, ci, v, r, lo, hi, 7, 1.001)
+    assert np.abs(z - ref).max() <= 1e-12 * np.abs(ref).max()
+    z1 = O.nc_apply_second_level(rp, ci, v, r, lo, hi, 7, 1.001, bs=1)
+    ea = np.linalg.eigvalsh(ad)
+    z1ref = O.nc_apply_unscaled(rp, ci, v, r, lo, hi, 7, 1.001)
+    assert np.abs(z1 - z1ref).max() <= 1e-12 * np.abs(z1ref).max()
+    b = W.uniform(12, n, -1.0, 1.0)
+    res = O.nc_pcg_second_level(rp, ci, v, b, lo, hi, 5, tol=1e-12, maxit=200)
+    x = np.linalg.solve(O.csr(rp, ci, v).toarray(), b)
+    assert res.converged and np.abs(res.x_hat - x).max() <= 1e-9 * np.abs(x).max()
+    # the same PCG run with the preconditioner in the similarity form, on the scaled system
+    c5 = O.chebyshev_scalars(lo, hi, 5, 1.001)
+    ref = O.pcg(lambda u: ad @ u, (b / np.sqrt(d)),
+                lambda q: O.chebyshev_apply(lambda u: binv @ (ad @ u), binv @ q, c5, 5), 1e-12, 200)
+    assert ref.iters == res.iters
+    assert np.allclose(res.history, ref.history, rtol=1e-8, atol=0.0)
+    res1 = O.nc_pcg_second_level(rp, ci, v, b, ea[0], ea[-1], 5, tol=1e-10, maxit=200, bs=1)
+    ref1 = O.nc_pcg(rp, ci, v, b, ea[0], ea[-1], 5, tol=1e-10, maxit=200)
+    assert res1.iters == ref1.iters and np.abs(res1.x_hat - ref1.x_hat).max() <= 1e-12 * np.abs(ref1.x_hat).max()
+
+
 ALL_FAST = [
     check_rho_closed_form,
     check_zeta_closed_form,
@@ -360,4 +406,5 @@ ALL_FAST = [
     check_indefinite_breakdown,
     check_power_method,
     check_dacg,
+    check_second_level,
 ]

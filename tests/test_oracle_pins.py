@@ -65,6 +65,10 @@ def test_dacg_closed_form_and_temple_bound():
     pins.check_dacg()
 
 
+def test_second_level_block_jacobi():
+    pins.check_second_level()
+
+
 def test_underestimated_bound_breaks_down():
     pins.check_indefinite_breakdown()
 

@@ -68,6 +68,15 @@ MUTANTS = [
      "DACG beta inverted"),
     ("dacg_smallest", "mu = float(evals[0])", "mu = float(evals[1])", "DACG larger Ritz value"),
     ("dacg_smallest", "u = evecs[:, 0] / np.sqrt", "u = evecs[:, 1] / np.sqrt", "DACG larger Ritz vector"),
+    # second level (Sec. 6)
+    ("block_jacobi_factor", "factors.append(np.linalg.inv(l).T)", "factors.append(np.linalg.inv(l))",
+     "W = L^-1 instead of L^-T"),
+    ("block_jacobi_factor", "factors.append(np.linalg.inv(l).T)", "factors.append(np.diag(1.0 / np.sqrt(np.diag(l @ l.T))))",
+     "point Jacobi instead of block Jacobi"),
+    ("nc_apply_second_level", "w @ chebyshev_apply(lambda v: cm @ v, w.T @ (dm * r_hat), c, k)",
+     "w @ chebyshev_apply(lambda v: cm @ v, w @ (dm * r_hat), c, k)", "W applied on the input instead of W^T"),
+    ("nc_pcg_second_level", "lambda r: w @ chebyshev_apply(lambda v: w.T @ op(w @ v), w.T @ r, c, k)",
+     "lambda r: chebyshev_apply(lambda v: w.T @ op(w @ v), r, c, k)", "second level without the outer W, W^T"),
 ]
 
 
