@@ -120,6 +120,12 @@ typedef struct pcheb_params {
   int32_t prec;             /* pcheb_precision */
   int32_t fuse_steps;
   int32_t form;             /* pcheb_form */
+  int32_t block_size;       /* first-level factor P0 = W W^T (closing remark of Sec. 6): 0 or 1 =
+                               the Jacobi scaling; 3 = node-block Jacobi (CSR/SELL, n % 3 == 0, the
+                               three rows of a node sharing one column pattern): W = blockdiag(L_I^-T)
+                               with L_I L_I^T the 3x3 diagonal block of node I, and the polynomial
+                               acts on W^T A W (bounds refer to its spectrum) */
+  int32_t reserved;         /* 0 */
 } pcheb_params;
 
 /* Flags of pcg_solve. */
@@ -220,6 +226,20 @@ size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int
  */
 pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
                                    double* lambda_min, double* lambda_max, hipStream_t stream);
+
+/*
+ * As pcheb_estimate_bounds, for the operator the preconditioner with first-level
+ * block size `block_size` acts on: 1 gives D^-1/2 A_hat D^-1/2 (the same as
+ * pcheb_estimate_bounds); 3 gives W^T A W on the node-block Jacobi factor of
+ * the Jacobi-scaled A (pcheb_params.block_size), that is L^-1 A_hat L^-T with
+ * L L^T the 3x3 diagonal blocks of A_hat (CSR/SELL, n % 3 == 0).  Allocates
+ * nsteps + 5 vectors for the duration of the call.  Errors as
+ * pcheb_estimate_bounds; INVALID also for another block size or a node whose
+ * rows differ in pattern, NOT_SPD for a block that is not positive definite.
+ */
+pcheb_status pcheb_estimate_bounds_block(const pcheb_operator* A, int32_t block_size, const double* v0,
+                                         int32_t nsteps, double* lambda_min, double* lambda_max,
+                                         hipStream_t stream);
 
 /*
  * The paper's bound estimates (Sec. 5.1) for the Jacobi-scaled operator

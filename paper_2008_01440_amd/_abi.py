@@ -65,6 +65,8 @@ class CParams(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("fuse_steps", ctypes.c_int32),
         ("form", ctypes.c_int32),
+        ("block_size", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -137,6 +139,8 @@ def load_library():
     lib.pcheb_footprint_bytes.restype = ctypes.c_size_t
     lib.pcheb_estimate_bounds.argtypes = [ctypes.POINTER(COperator), vp, i32, ctypes.POINTER(f64),
                                           ctypes.POINTER(f64), vp]
+    lib.pcheb_estimate_bounds_block.argtypes = [ctypes.POINTER(COperator), i32, vp, i32, ctypes.POINTER(f64),
+                                                ctypes.POINTER(f64), vp]
     lib.pcheb_estimate_bounds_pdacg.argtypes = [ctypes.POINTER(COperator), vp, i32, f64, i32, ctypes.POINTER(f64),
                                                 ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(f64), vp]
     lib.pcheb_fill_uniform.argtypes = [vp, i64, ctypes.c_uint64, f64, f64, vp]
@@ -149,7 +153,7 @@ def load_library():
     lib.pserve_get_stats.argtypes = [vp, ctypes.POINTER(CServeStats)]
     lib.pserve_destroy.argtypes = [vp]
     for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
-                 "pcheb_estimate_bounds", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
+                 "pcheb_estimate_bounds", "pcheb_estimate_bounds_block", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
                  "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -253,18 +257,20 @@ class Handle:
         pcheb_destroy(self)
 
 
-def _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form="chebyshev"):
+def _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form="chebyshev", block_size=1):
     return CParams(k=k, lambda_min=lambda_min, lambda_max=lambda_max, theta_scale=theta_scale,
                    prec=PREC[prec] if isinstance(prec, str) else int(prec), fuse_steps=fuse_steps,
-                   form=FORM[form] if isinstance(form, str) else int(form))
+                   form=FORM[form] if isinstance(form, str) else int(form), block_size=int(block_size))
 
 
 def pcheb_setup(op: Operator, k: int, lambda_min: float, lambda_max: float, theta_scale: float = 1.001,
-                prec: str = "f64", fuse_steps: int = 1, stream=None, form: str = "chebyshev") -> Handle:
+                prec: str = "f64", fuse_steps: int = 1, stream=None, form: str = "chebyshev",
+                block_size: int = 1) -> Handle:
     """form: "chebyshev" (the recurrence of Alg. 2) or "newton" (the recursion of Alg. 1,
-    k = 2^nlev - 1)."""
+    k = 2^nlev - 1).  block_size 3: the second-level preconditioner on the node-block Jacobi
+    factor (CSR/SELL); the bounds then refer to W^T A W."""
     lib = load_library()
-    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form)
+    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form, block_size)
     out = ctypes.c_void_p()
     _check(lib.pcheb_setup(ctypes.byref(op.c), ctypes.byref(p), _stream(stream), ctypes.byref(out)))
     return Handle(out, op, p)
@@ -315,15 +321,21 @@ def pcheb_destroy(h: Handle):
 
 def pcheb_footprint_bytes(op: Operator, k: int, lambda_min: float = 0.1, lambda_max: float = 2.0,
                           theta_scale: float = 1.001, prec: str = "f64", nrhs: int = 1, fuse_steps: int = 1,
-                          form: str = "chebyshev") -> int:
-    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form)
+                          form: str = "chebyshev", block_size: int = 1) -> int:
+    p = _params(k, lambda_min, lambda_max, theta_scale, prec, fuse_steps, form, block_size)
     return int(load_library().pcheb_footprint_bytes(ctypes.byref(op.c), ctypes.byref(p), nrhs))
 
 
-def pcheb_estimate_bounds(op: Operator, v0, nsteps: int = 30, stream=None):
+def pcheb_estimate_bounds(op: Operator, v0, nsteps: int = 30, stream=None, block_size: int = 1):
+    """Lanczos extreme Ritz values of D^-1/2 A_hat D^-1/2 (block_size 1) or of the second-level
+    operator W^T A W on the node-block Jacobi factor (block_size 3)."""
     lo, hi = ctypes.c_double(), ctypes.c_double()
-    _check(load_library().pcheb_estimate_bounds(ctypes.byref(op.c), _dptr(v0, "float64"), nsteps,
-                                                ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
+    if block_size == 1:
+        _check(load_library().pcheb_estimate_bounds(ctypes.byref(op.c), _dptr(v0, "float64"), nsteps,
+                                                    ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
+    else:
+        _check(load_library().pcheb_estimate_bounds_block(ctypes.byref(op.c), int(block_size), _dptr(v0, "float64"),
+                                                          nsteps, ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
     return lo.value, hi.value
 
 

@@ -180,6 +180,50 @@ static double tridiag_eig(const std::vector<double>& a, const std::vector<double
   return 0.5 * (lo + hi);
 }
 
+// Node blocks: u = W v = L^-T v per node (M = L^-1 stored row-major lower).
+__global__ void k_node_wv(const double* __restrict__ v, double* __restrict__ u, const double* __restrict__ lfac,
+                          int64_t nodes) {
+  for (int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; I < nodes; I += int64_t(gridDim.x) * blockDim.x) {
+    const double* m = lfac + 6 * I;
+    const double v0 = v[3 * I], v1 = v[3 * I + 1], v2 = v[3 * I + 2];
+    u[3 * I] = m[0] * v0 + m[1] * v1 + m[3] * v2;
+    u[3 * I + 1] = m[2] * v1 + m[4] * v2;
+    u[3 * I + 2] = m[5] * v2;
+  }
+}
+
+// Node blocks: w <- W^T w = L^-1 w per node, in place.
+__global__ void k_node_wtw(double* __restrict__ w, const double* __restrict__ lfac, int64_t nodes) {
+  for (int64_t I = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; I < nodes; I += int64_t(gridDim.x) * blockDim.x) {
+    const double* m = lfac + 6 * I;
+    const double w0 = w[3 * I], w1 = w[3 * I + 1], w2 = w[3 * I + 2];
+    w[3 * I] = m[0] * w0;
+    w[3 * I + 1] = m[1] * w0 + m[2] * w1;
+    w[3 * I + 2] = m[3] * w0 + m[4] * w1 + m[5] * w2;
+  }
+}
+
+// w = C v for the operator whose bounds are estimated: C = D^-1/2 A_hat D^-1/2
+// (one fused launch), or with node blocks C = W^T A W on the block Jacobi
+// factor W of the Jacobi-scaled A, i.e. C = L^-1 A_hat L^-T with L L^T the 3x3
+// diagonal blocks of A_hat (the diagonal scaling cancels).
+struct ScaledProduct {
+  Handle* h;
+  const double* isd;  // D^-1/2 (point scaling)
+  double* u;          // node blocks: workspace for W v
+  hipStream_t s;
+  void operator()(const double* v, double* w) const {
+    const int64_t n = h->n;
+    if (h->bs == 3) {
+      k_node_wv<<<kLzGrid, kBlock, 0, s>>>(v, u, h->lfac, n / 3);
+      launch_ahat(*h, InVec<double>{u, 0}, EpiStore<double>{w, nullptr, nullptr, 0}, 0, 1, s);
+      k_node_wtw<<<kLzGrid, kBlock, 0, s>>>(w, h->lfac, n / 3);
+    } else {
+      launch_ahat(*h, InScaled{v, isd, n}, EpiScaledStore{w, isd, nullptr, nullptr, n}, 0, 1, s);
+    }
+  }
+};
+
 static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double* lmax, hipStream_t s) {
   const int64_t n = h.n;
   const int m = int(std::min<int64_t>(steps, n));
@@ -197,6 +241,8 @@ static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double
   double* nrm0 = inv + 1;
   const uint32_t g = 2048;
   k_isqrt_diag<<<g, kBlock, 0, s>>>(h.invd, 1.0 / 6.0, isd, n);
+  double* u = h.bs == 3 ? static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double))) : nullptr;
+  const ScaledProduct product{&h, isd, u, s};
 
   // v_0 = v0 / ||v0|| (the one host check: a zero or non-finite start vector is an error)
   k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(v0, 0, 0, 1, v0, n, partial);
@@ -210,7 +256,7 @@ static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double
   for (int j = 0; j < m; ++j) {
     const double* vj = V + int64_t(j) * ldv;
     const int cols = j + 1;
-    launch_ahat(h, InScaled{vj, isd, n}, EpiScaledStore{w, isd, nullptr, nullptr, n}, 0, 1, s);
+    product(vj, w);
     // pass 1: c = V^T w (alpha_j = c[j]); then w -= V c
     for (int c0 = 0; c0 < cols; c0 += kCols) {
       const int nc = std::min(kCols, cols - c0);
@@ -601,8 +647,12 @@ using namespace pcheb;
 namespace {
 
 // Arguments every estimator checks; the handle holds the operator for the products.
-void estimator_setup(Handle& h, const pcheb_operator* A, const double* v0, hipStream_t stream) {
+void estimator_setup(Handle& h, const pcheb_operator* A, const double* v0, hipStream_t stream, int block_size = 1) {
+  if (block_size != 1 && block_size != 3) fail(PCHEB_INVALID, "block_size must be 1 or 3");
   if (!A || !v0) fail(PCHEB_INVALID, "null argument");
+  if (block_size == 3 && A->kind != PCHEB_OP_CSR && A->kind != PCHEB_OP_SELL)
+    fail(PCHEB_INVALID, "block_size 3 needs a CSR or SELL operator");
+  if (block_size == 3 && A->n % 3 != 0) fail(PCHEB_INVALID, "block_size 3 needs n to be a multiple of 3");
   if (A->n <= 0) fail(PCHEB_INVALID, "n must be positive");
   if ((A->kind == PCHEB_OP_CSR || A->kind == PCHEB_OP_SELL) && (!A->rowptr || !A->colind || !A->values))
     fail(PCHEB_INVALID, "CSR arrays must be non-null");
@@ -613,17 +663,19 @@ void estimator_setup(Handle& h, const pcheb_operator* A, const double* v0, hipSt
   h.op = *A;
   h.op.kind = (A->kind == PCHEB_OP_SELL) ? PCHEB_OP_CSR : A->kind;  // the product itself is all that is needed
   h.prm.prec = PCHEB_F64;
+  h.prm.block_size = block_size;
   h.n = A->n;
   setup_operator(h, stream);
 }
 
 template <class F>
-pcheb_status run_estimator(const pcheb_operator* A, const double* v0, hipStream_t stream, F&& body) {
+pcheb_status run_estimator(const pcheb_operator* A, const double* v0, hipStream_t stream, F&& body,
+                           int block_size = 1) {
   try {
     set_last_error("");
     Handle h;
     try {
-      estimator_setup(h, A, v0, stream);
+      estimator_setup(h, A, v0, stream, block_size);
       body(h);
     } catch (...) {
       (void)hipStreamSynchronize(stream);
@@ -659,6 +711,25 @@ extern "C" pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const dou
     return PCHEB_INVALID;
   }
   return run_estimator(A, v0, stream, [&](Handle& h) { lanczos(h, v0, nsteps, lambda_min, lambda_max, stream); });
+}
+
+extern "C" pcheb_status pcheb_estimate_bounds_block(const pcheb_operator* A, int32_t block_size, const double* v0,
+                                                    int32_t nsteps, double* lambda_min, double* lambda_max,
+                                                    hipStream_t stream) {
+  if (!lambda_min || !lambda_max) {
+    set_last_error("null argument");
+    return PCHEB_INVALID;
+  }
+  if (v0 && reinterpret_cast<uintptr_t>(v0) % 16 != 0) {
+    set_last_error("v0 must be 16-byte aligned");
+    return PCHEB_INVALID;
+  }
+  if (nsteps < 1 || nsteps > 1000) {
+    set_last_error("nsteps must be in [1, 1000]");
+    return PCHEB_INVALID;
+  }
+  return run_estimator(
+      A, v0, stream, [&](Handle& h) { lanczos(h, v0, nsteps, lambda_min, lambda_max, stream); }, block_size);
 }
 
 extern "C" pcheb_status pcheb_estimate_bounds_pdacg(const pcheb_operator* A, const double* v0, int32_t power_iters,

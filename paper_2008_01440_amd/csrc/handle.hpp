@@ -57,6 +57,11 @@ struct Handle {
   int32_t* sell_perm = nullptr; // null when sigma == 1
   float* rho_lo = nullptr;      // STENCIL27H, float recurrences: 1 / (2 kappa) per cell
   float* invd_lo = nullptr;     // STENCIL27H, float recurrences: D^-1 rounded to float
+  int bs = 1;                   // first-level block size (1: Jacobi scaling, 3: node blocks)
+  double* binv = nullptr;       // bs == 3: per node, the symmetric inverse of its 3x3 diagonal block
+                                // (xx, xy, xz, yy, yz, zz)
+  double* lfac = nullptr;       // bs == 3: per node, L^-1 of the block's Cholesky factor L
+                                // (row-major lower triangle: 00, 10, 11, 20, 21, 22)
 
   // solve workspace for `cap` right-hand sides (slots); vectors of slot j start
   // at j * ldw elements.  Allocated on demand, separately from the operator data.

@@ -162,11 +162,93 @@ __global__ void k_scale_rows(const int32_t* rowptr, const double* val, const dou
   }
 }
 
+// Node blocks (block size 3, the second-level construction of Sec. 6 on the
+// first-level factor P0 = W W^T): node I owns rows 3I, 3I+1, 3I+2, which must
+// share one column pattern.  Per node: the 3x3 diagonal block B = L L^T
+// (Cholesky), M = L^-1 (so W = blockdiag(M^T)) and B^-1 = M^T M.  Flags a block
+// that is not positive definite (bit 0) or rows of a node with different
+// patterns (bit 1).
+__global__ void k_node_blocks(const int32_t* rowptr, const int32_t* col, const double* val, int64_t nodes,
+                              double* binv, double* lfac, int* bad) {
+  GRID_STRIDE(I, nodes) {
+    const int64_t r0 = 3 * I;
+    const int32_t b0 = rowptr[r0], len = rowptr[r0 + 1] - b0;
+    bool same = rowptr[r0 + 2] - rowptr[r0 + 1] == len && rowptr[r0 + 3] - rowptr[r0 + 2] == len;
+    double b[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int a = 0; a < 3 && same; ++a) {
+      const int32_t ba = rowptr[r0 + a];
+      for (int32_t t = 0; t < len; ++t) {
+        const int32_t c = col[ba + t];
+        if (c != col[b0 + t]) same = false;
+        const int64_t d = int64_t(c) - r0;
+        if (d >= 0 && d < 3) b[a][d] += val[ba + t];
+      }
+    }
+    if (!same) {
+      atomicOr(bad, 2);
+      continue;
+    }
+    const double d00 = b[0][0];
+    const double l00 = sqrt(d00);
+    const double l10 = b[1][0] / l00, l20 = b[2][0] / l00;
+    const double d11 = b[1][1] - l10 * l10;
+    const double l11 = sqrt(d11);
+    const double l21 = (b[2][1] - l20 * l10) / l11;
+    const double d22 = b[2][2] - l20 * l20 - l21 * l21;
+    const double l22 = sqrt(d22);
+    if (!(d00 > 0.0) || !(d11 > 0.0) || !(d22 > 0.0) || !isfinite(l21) || !isfinite(d22)) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    const double m00 = 1.0 / l00, m11 = 1.0 / l11, m22 = 1.0 / l22;
+    const double m10 = -l10 * m00 * m11;
+    const double m21 = -l21 * m11 * m22;
+    const double m20 = -(l20 * m00 + l21 * m10) * m22;
+    double* lf = lfac + 6 * I;
+    lf[0] = m00;
+    lf[1] = m10;
+    lf[2] = m11;
+    lf[3] = m20;
+    lf[4] = m21;
+    lf[5] = m22;
+    double* bi = binv + 6 * I;  // (M^T M)_ij = sum over k >= max(i, j) of M_ki M_kj
+    bi[0] = m00 * m00 + m10 * m10 + m20 * m20;
+    bi[1] = m10 * m11 + m20 * m21;
+    bi[2] = m20 * m22;
+    bi[3] = m11 * m11 + m21 * m21;
+    bi[4] = m21 * m22;
+    bi[5] = m22 * m22;
+  }
+}
+
+// Row a (0..2) of a node's symmetric B^-1 stored as (xx, xy, xz, yy, yz, zz).
+__device__ __forceinline__ void binv_row(const double* bi, int a, double& c0, double& c1, double& c2) {
+  c0 = a == 0 ? bi[0] : (a == 1 ? bi[1] : bi[2]);
+  c1 = a == 0 ? bi[1] : (a == 1 ? bi[3] : bi[4]);
+  c2 = a == 0 ? bi[2] : (a == 1 ? bi[4] : bi[5]);
+}
+
+// Values of B^-1 A_hat in the storage precision: row 3I+a is the combination of
+// the node's three rows (same pattern, so entry t of each is one column).
+template <class T>
+__global__ void k_scale_rows_node(const int32_t* rowptr, const double* val, const double* binv, int64_t n, T* out) {
+  GRID_STRIDE(i, n) {
+    const int64_t I = i / 3;
+    double c0, c1, c2;
+    binv_row(binv + 6 * I, int(i - 3 * I), c0, c1, c2);
+    const int32_t b = rowptr[i], e = rowptr[i + 1];
+    const int32_t q0 = rowptr[3 * I], q1 = rowptr[3 * I + 1], q2 = rowptr[3 * I + 2];
+    for (int32_t t = 0; t < e - b; ++t)
+      Store<T>::st(out, b + t, typename Store<T>::acc(c0 * val[q0 + t] + c1 * val[q1 + t] + c2 * val[q2 + t]));
+  }
+}
+
 // Fill the SELL-C-sigma arrays (C = 64) from CSR; padding gets column 0, value 0.
+// The recurrence values are D^-1 A_hat (binv null) or B^-1 A_hat (node blocks).
 template <class T>
 __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* col, const double* val, const double* invd,
-                            const int32_t* perm, const int64_t* cptr, const int32_t* clen, int64_t n,
-                            int64_t nchunks, int32_t* scol, double* saval, T* sbval) {
+                            const double* binv, const int32_t* perm, const int64_t* cptr, const int32_t* clen,
+                            int64_t n, int64_t nchunks, int32_t* scol, double* saval, T* sbval) {
   GRID_STRIDE(pos, nchunks * kWave) {
     const int64_t c = pos / kWave;
     const int lane = int(pos % kWave);
@@ -183,7 +265,16 @@ __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* col, const dou
       if (j < rl) {
         scol[e] = col[b + j];
         saval[e] = val[b + j];
-        Store<T>::st(sbval, e, typename Store<T>::acc(val[b + j] * invd[row]));
+        double bv;
+        if (binv) {
+          const int64_t I = row / 3;
+          double c0, c1, c2;
+          binv_row(binv + 6 * I, int(row - 3 * I), c0, c1, c2);
+          bv = c0 * val[rowptr[3 * I] + j] + c1 * val[rowptr[3 * I + 1] + j] + c2 * val[rowptr[3 * I + 2] + j];
+        } else {
+          bv = val[b + j] * invd[row];
+        }
+        Store<T>::st(sbval, e, typename Store<T>::acc(bv));
       } else {
         scol[e] = 0;
         saval[e] = 0.0;
@@ -330,6 +421,58 @@ __global__ void k_prep(const double* r, int64_t ldr, T* s, T* y0, int64_t ldw, I
       Store<T>::st(y0, i, acc(si * inv_theta));
     }
   }
+}
+
+// Node blocks: s = B^-1 r and y_0 = s / theta' in the storage precision.
+template <class T>
+__global__ void k_node_prep(const double* r, int64_t ldr, T* s, T* y0, int64_t ldw, const double* binv,
+                            double inv_theta, int64_t nodes, const DevState* guard, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  r += slot * ldr;
+  s += slot * ldw;
+  y0 += slot * ldw;
+  using acc = typename Store<T>::acc;
+  GRID_STRIDE(I, nodes) {
+    const double* bi = binv + 6 * I;
+    const int64_t i = 3 * I;
+    const double r0 = r[i], r1 = r[i + 1], r2 = r[i + 2];
+    const double s0 = bi[0] * r0 + bi[1] * r1 + bi[2] * r2;
+    const double s1 = bi[1] * r0 + bi[3] * r1 + bi[4] * r2;
+    const double s2 = bi[2] * r0 + bi[4] * r1 + bi[5] * r2;
+    Store<T>::st(s, i, acc(s0));
+    Store<T>::st(s, i + 1, acc(s1));
+    Store<T>::st(s, i + 2, acc(s2));
+    Store<T>::st(y0, i, acc(s0 * inv_theta));
+    Store<T>::st(y0, i + 1, acc(s1 * inv_theta));
+    Store<T>::st(y0, i + 2, acc(s2 * inv_theta));
+  }
+}
+
+// Node blocks, degree 0: z = B^-1 r / theta' (block Jacobi), optionally with (r, z), (z, q).
+__global__ void k_node_jacobi(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q,
+                              const double* binv, double inv_theta, int64_t nodes, const DevState* guard,
+                              ReduceBuf rb, int dots, int flexible, int slot0) {
+  const int slot = slot0 + int(blockIdx.y);
+  if (guard && guard[slot].done != kRunning) return;
+  r += slot * ldr;
+  z += slot * ldz;
+  if (q) q += slot * ldz;
+  double part[2] = {0.0, 0.0};
+  GRID_STRIDE(I, nodes) {
+    const double* bi = binv + 6 * I;
+    const int64_t i = 3 * I;
+    const double r0 = r[i], r1 = r[i + 1], r2 = r[i + 2];
+    const double z0 = (bi[0] * r0 + bi[1] * r1 + bi[2] * r2) * inv_theta;
+    const double z1 = (bi[1] * r0 + bi[3] * r1 + bi[4] * r2) * inv_theta;
+    const double z2 = (bi[2] * r0 + bi[4] * r1 + bi[5] * r2) * inv_theta;
+    z[i] = z0;
+    z[i + 1] = z1;
+    z[i + 2] = z2;
+    part[0] += r0 * z0 + r1 * z1 + r2 * z2;
+    if (flexible) part[1] += z0 * q[i] + z1 * q[i + 1] + z2 * q[i + 2];
+  }
+  if (dots) block_partial<2>(part, rb, slot);
 }
 
 // Degree 0: z = D^-1 r / theta' (the diagonal preconditioner), optionally with
@@ -520,6 +663,20 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
   }
 }
 
+// Preconditioner input s = D^-1 r (or B^-1 r with node blocks) and y_0 = s / theta'.
+template <class T>
+static void enqueue_prep(Handle& h, Slots sl, const double* r, int64_t ldr, const DevState* guard, hipStream_t s) {
+  const int64_t n = h.n;
+  if (h.bs == 3)
+    k_node_prep<T><<<dim3(flat_grid(n / 3), sl.count), kBlock, 0, s>>>(
+        r, ldr, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), h.ldw, h.binv, 1.0 / h.theta, n / 3,
+        guard, sl.first);
+  else
+    k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(r, ldr, reinterpret_cast<T*>(h.s),
+                                                              reinterpret_cast<T*>(h.Y[0]), h.ldw, invdiag(h),
+                                                              1.0 / h.theta, n, guard, sl.first);
+}
+
 // Stand-alone application r -> z (caller vectors) on slot 0 of the workspace.
 template <class T>
 static void enqueue_newton(Handle& h, Slots sl, double* z, int64_t ldz, const double* r, int64_t ldr,
@@ -529,12 +686,15 @@ template <class T>
 static void enqueue_apply_one(Handle& h, const double* r, double* z, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
-    k_jacobi<<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, z, 0, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr,
-                                                      h.rb(), 0, 0, 0);
+    if (h.bs == 3)
+      k_node_jacobi<<<dim3(flat_grid(n / 3), 1), kBlock, 0, s>>>(r, 0, z, 0, nullptr, h.binv, 1.0 / h.theta, n / 3,
+                                                                  nullptr, h.rb(), 0, 0, 0);
+    else
+      k_jacobi<<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, z, 0, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr,
+                                                        h.rb(), 0, 0, 0);
     return;
   }
-  k_prep<T><<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]),
-                                                     h.ldw, invdiag(h), 1.0 / h.theta, n, nullptr, 0);
+  enqueue_prep<T>(h, Slots{0, 1}, r, 0, nullptr, s);
   if (h.prm.form == PCHEB_FORM_NEWTON)
     enqueue_newton<T>(h, Slots{0, 1}, z, 0, r, 0, nullptr, false, 0, 0, nullptr, s);
   else
@@ -664,6 +824,11 @@ static void validate(const pcheb_operator* A, const pcheb_params* p) {
   if (p->form == PCHEB_FORM_NEWTON && p->prec == PCHEB_BF16)
     fail(PCHEB_INVALID, "the Newton form needs F64 or F32 storage (its intermediates compound BF16 rounding)");
   if (A->n <= 0) fail(PCHEB_INVALID, "n must be positive");
+  if (p->block_size != 0 && p->block_size != 1 && p->block_size != 3)
+    fail(PCHEB_INVALID, "block_size must be 1 or 3");
+  if (p->block_size == 3 && A->kind != PCHEB_OP_CSR && A->kind != PCHEB_OP_SELL)
+    fail(PCHEB_INVALID, "block_size 3 needs a CSR or SELL operator");
+  if (p->block_size == 3 && A->n % 3 != 0) fail(PCHEB_INVALID, "block_size 3 needs n to be a multiple of 3");
   switch (A->kind) {
     case PCHEB_OP_CSR:
     case PCHEB_OP_SELL:
@@ -728,8 +893,12 @@ static void build_scaled_values(Handle& h, hipStream_t s) {
   const pcheb_operator& op = h.op;
   if (op.kind == PCHEB_OP_CSR) {
     h.csr_bval = dev_alloc(h, size_t(op.nnz) * sizeof(T));
-    k_scale_rows<T><<<flat_grid(h.n), kBlock, 0, s>>>(op.rowptr, op.values, h.invd, h.n,
-                                                     reinterpret_cast<T*>(h.csr_bval));
+    if (h.bs == 3)
+      k_scale_rows_node<T><<<flat_grid(h.n), kBlock, 0, s>>>(op.rowptr, op.values, h.binv, h.n,
+                                                            reinterpret_cast<T*>(h.csr_bval));
+    else
+      k_scale_rows<T><<<flat_grid(h.n), kBlock, 0, s>>>(op.rowptr, op.values, h.invd, h.n,
+                                                       reinterpret_cast<T*>(h.csr_bval));
     PCHEB_HIP_CHECK(hipGetLastError());
   } else if (op.kind == PCHEB_OP_SELL) {
     // row lengths on the host, sorted within windows of sigma rows (longest first)
@@ -777,8 +946,8 @@ static void build_scaled_values(Handle& h, hipStream_t s) {
     PCHEB_HIP_CHECK(hipMemcpyAsync(h.sell_ptr, cptr.data(), cptr.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     PCHEB_HIP_CHECK(hipMemcpyAsync(h.sell_len, clen.data(), clen.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     k_sell_fill<T><<<flat_grid(h.nchunks * kWave), kBlock, 0, s>>>(
-        op.rowptr, op.colind, op.values, h.invd, dperm, h.sell_ptr, h.sell_len, h.n, h.nchunks, h.sell_col,
-        h.sell_aval, reinterpret_cast<T*>(h.sell_bval));
+        op.rowptr, op.colind, op.values, h.invd, h.binv, dperm, h.sell_ptr, h.sell_len, h.n, h.nchunks,
+        h.sell_col, h.sell_aval, reinterpret_cast<T*>(h.sell_bval));
     PCHEB_HIP_CHECK(hipGetLastError());
     PCHEB_HIP_CHECK(hipStreamSynchronize(s));  // host vectors above go out of scope
   }
@@ -791,10 +960,17 @@ void setup_operator(Handle& h, hipStream_t s) {
   PCHEB_HIP_CHECK(hipGetDevice(&h.device));
   int* bad = static_cast<int*>(dev_alloc(h, sizeof(int)));
   PCHEB_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
+  h.bs = h.prm.block_size == 3 ? 3 : 1;
   if (op.kind == PCHEB_OP_CSR || op.kind == PCHEB_OP_SELL) {
     h.invd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
     k_csr_invdiag<<<flat_grid(n), kBlock, 0, s>>>(op.rowptr, op.colind, op.values, n, h.invd, bad);
     h.lanes = pick_lanes(n, op.nnz);
+    if (h.bs == 3) {
+      h.binv = static_cast<double*>(dev_alloc(h, size_t(n / 3) * 6 * sizeof(double)));
+      h.lfac = static_cast<double*>(dev_alloc(h, size_t(n / 3) * 6 * sizeof(double)));
+      k_node_blocks<<<flat_grid(n / 3), kBlock, 0, s>>>(op.rowptr, op.colind, op.values, n / 3, h.binv, h.lfac,
+                                                         bad);
+    }
   } else if (op.kind == PCHEB_OP_STENCIL27H) {
     h.invd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
     k_h27_invdiag<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, op.nx, op.ny, op.nz, h.invd, bad);
@@ -808,7 +984,8 @@ void setup_operator(Handle& h, hipStream_t s) {
   int bad_host = 0;
   PCHEB_HIP_CHECK(hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   PCHEB_HIP_CHECK(hipStreamSynchronize(s));
-  if (bad_host) fail(PCHEB_NOT_SPD, "operator has a non-positive diagonal entry or coefficient");
+  if (bad_host & 2) fail(PCHEB_INVALID, "block_size 3: the three rows of a node must share one column pattern");
+  if (bad_host) fail(PCHEB_NOT_SPD, "operator has a non-positive diagonal entry, coefficient or 3x3 block");
 }
 
 // Recurrence scalars and the scaled operator copies.
@@ -860,6 +1037,7 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
     if (A->sell_sigma > 1) b += size_t(n) * 4;
   }
   if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 8 : 0);
+  if (p->block_size == 3) b += size_t(n / 3) * 12 * 8;  // node inverses and factors
   const int ny = (A->kind == PCHEB_OP_STENCIL7 && p->fuse_steps >= 2) ? 4 : 3;
   int nt = 0;  // Newton form: 2 nlev + 1 iterate vectors
   if (p->form == PCHEB_FORM_NEWTON)
@@ -892,15 +1070,20 @@ template <class T>
 static void enqueue_precond(Handle& h, Slots sl, int init, int flexible, StepTimer* timer, hipStream_t s) {
   const int64_t n = h.n;
   if (h.prm.k == 0) {
+    if (h.bs == 3) {
+      const uint32_t g = flat_grid(n / 3);
+      k_node_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, h.binv, 1.0 / h.theta, n / 3,
+                                                          h.st, h.rb(), 1, flexible, sl.first);
+      k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
+      return;
+    }
     const uint32_t g = pair_grid(n);
     k_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, invdiag(h), 1.0 / h.theta, n, h.st,
                                                   h.rb(), 1, flexible, sl.first);
     k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
     return;
   }
-  k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(h.r, h.ldw, reinterpret_cast<T*>(h.s),
-                                                            reinterpret_cast<T*>(h.Y[0]), h.ldw, invdiag(h),
-                                                            1.0 / h.theta, n, h.st, sl.first);
+  enqueue_prep<T>(h, sl, h.r, h.ldw, h.st, s);
   if (h.prm.form == PCHEB_FORM_NEWTON)
     enqueue_newton<T>(h, sl, h.z, h.ldw, h.r, h.ldw, h.q, true, init, flexible, h.st, s);
   else
@@ -945,7 +1128,12 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
     enqueue_precond<T>(h, sl, 0, flexible, timer, s);
     return;
   }
-  if (h.prm.k == 0) {
+  if (h.bs == 3) {  // node blocks: the preconditioner input needs whole nodes, so it is a pass of its own
+    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
+                                           n, st, h.rb(), sl.first);
+    k_finalize<3, FinUpdate<2>><<<sl.count, kBlock, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
+    enqueue_precond<T>(h, sl, 0, flexible, timer, s);
+  } else if (h.prm.k == 0) {
     k_update<double, 1><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, h.z,
                                                 1.0 / h.theta, n, st, h.rb(), sl.first);
     k_finalize<3, FinUpdate<1>><<<sl.count, kBlock, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st, sl.first);
@@ -954,7 +1142,10 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
                                            reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb(),
                                            sl.first);
     k_finalize<3, FinUpdate<0>><<<sl.count, kBlock, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st, sl.first);
-    enqueue_steps<T>(h, sl, h.z, h.r, h.q, true, 0, flexible, st, timer, s);
+    if (h.prm.form == PCHEB_FORM_NEWTON)
+      enqueue_newton<T>(h, sl, h.z, h.ldw, h.r, h.ldw, h.q, true, 0, flexible, st, s);
+    else
+      enqueue_steps<T>(h, sl, h.z, h.r, h.q, true, 0, flexible, st, timer, s);
   }
 }
 

@@ -28,7 +28,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
-                 "pcheb_footprint_bytes", "pcheb_estimate_bounds", "pcheb_estimate_bounds_pdacg", "pserve_create",
+                 "pcheb_footprint_bytes", "pcheb_estimate_bounds", "pcheb_estimate_bounds_pdacg",
+                 "pcheb_estimate_bounds_block", "pserve_create",
                  "pserve_submit", "pserve_poll",
                  "pserve_wait", "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         assert name in fns
@@ -69,9 +70,10 @@ def test_struct_layout_matches_c(tmp_path):
             assert int(lines[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
 
 
-def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0, form=0):
+def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0, form=0, block_size=0):
     lib = pc.load_library()
-    p = _abi.CParams(k=k, lambda_min=lmin, lambda_max=lmax, theta_scale=s, prec=prec, fuse_steps=1, form=form)
+    p = _abi.CParams(k=k, lambda_min=lmin, lambda_max=lmax, theta_scale=s, prec=prec, fuse_steps=1, form=form,
+                     block_size=block_size)
     out = ctypes.c_void_p()
     return lib.pcheb_setup(ctypes.byref(op.c), ctypes.byref(p), None, ctypes.byref(out))
 
@@ -80,6 +82,7 @@ def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0, form=0):
     (dict(k=-1), "degree"), (dict(k=1001), "degree"), (dict(lmin=0.0), "lambda"), (dict(lmin=2.0), "lambda"),
     (dict(s=0.99), "theta_scale"), (dict(prec=7), "precision"), (dict(form=2), "form"),
     (dict(k=5, form=1), "Newton"), (dict(k=6, form=1), "Newton"), (dict(k=7, form=1, prec=2), "Newton"),
+    (dict(block_size=2), "block_size"), (dict(block_size=3), "block_size"), (dict(block_size=-1), "block_size"),
 ])
 def test_setup_rejects_bad_parameters(kw, what):
     assert _setup_status(pc.Operator.stencil7(4), **kw) == 1
@@ -111,6 +114,7 @@ def test_null_arguments():
     assert lib.pcheb_estimate_bounds(None, None, 30, ctypes.byref(lo), ctypes.byref(hi), None) == 1
     assert lib.pcheb_estimate_bounds_pdacg(None, None, 30, 1e-2, 100, ctypes.byref(lo), ctypes.byref(hi), None, None,
                                            None) == 1
+    assert lib.pcheb_estimate_bounds_block(None, 3, None, 30, ctypes.byref(lo), ctypes.byref(hi), None) == 1
 
 
 def test_pdacg_argument_checks():
@@ -161,3 +165,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_abi, "_PKG", str(tmp_path))
     with pytest.raises(RuntimeError, match="missing"):
         _abi.load_library()
+
+
+def test_block_size_needs_csr_with_node_rows():
+    """The node-block first level is for CSR/SELL operators whose size is a multiple of 3."""
+    csr = _abi.Operator(_abi.COperator(kind=0, n=10, rowptr=8, colind=8, values=8, nnz=10))
+    assert _setup_status(csr, block_size=3) == 1 and "multiple of 3" in pc.pcheb_last_error()
+    lib = pc.load_library()
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    assert lib.pcheb_estimate_bounds_block(ctypes.byref(pc.Operator.stencil7(3).c), 3, None, 30, ctypes.byref(lo),
+                                           ctypes.byref(hi), None) == 1
+    assert lib.pcheb_estimate_bounds_block(ctypes.byref(csr.c), 2, None, 30, ctypes.byref(lo),
+                                           ctypes.byref(hi), None) == 1 and "block_size" in pc.pcheb_last_error()

@@ -208,6 +208,63 @@ def test_power_dacg_rejects_zero_start(pc):
         pc.pcheb_estimate_bounds_pdacg(op, torch.zeros(512, dtype=torch.float64, device=DEV), 5, 1e-2, 10)
 
 
+def _second_level_bounds(c):
+    """Bounds of W^T A W (the operator of the node-block second level) from the oracle's Lanczos."""
+    _, _, _, cm = oracle.second_level_operator(c.rp, c.ci, c.v)
+    lo, hi = oracle.lanczos_extremes(lambda x: cm @ x, W.uniform(7, c.n, 0.5, 1.5), 30)
+    return lo, 1.01 * hi
+
+
+@pytest.mark.parametrize("name", ["csr_el", "sell_el"])
+@pytest.mark.parametrize("prec,k,form", [("f64", 0, "chebyshev"), ("f64", 10, "chebyshev"), ("f32", 10, "chebyshev"),
+                                         ("f64", 7, "newton")])
+def test_second_level_apply(pc, name, prec, k, form):
+    """W p_k(W^T A W) W^T on the node-block Jacobi factor (Sec. 6) against the oracle's explicit
+    form; the library runs the recurrence on B^-1 A_hat with input B^-1 r (k = 0: block Jacobi)."""
+    c = case(name)
+    lo, hi = _second_level_bounds(c)
+    r = W.uniform(4, c.n, -1.0, 1.0)
+    ref = oracle.nc_apply_second_level(c.rp, c.ci, c.v, r, lo, hi, k, 1.001)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, lo, hi, 1.001, prec, form=form, block_size=3) as h:
+        z = torch.empty(c.n, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, _t(r), z)
+        torch.cuda.synchronize()
+    assert rel_inf(z.cpu().numpy(), ref) <= APPLY_TOL[prec]
+
+
+@pytest.mark.parametrize("name,k,prec", [("csr_el", 10, "f64"), ("sell_el", 10, "f32"), ("csr_el", 0, "f64"),
+                                         ("sell_el", 7, "f32")])
+def test_second_level_solve(pc, name, k, prec):
+    c = case(name)
+    lo, hi = _second_level_bounds(c)
+    _, b = manufactured_rhs(name)
+    flexible = prec != "f64"
+    ref = oracle.nc_pcg_second_level(c.rp, c.ci, c.v, b, lo, hi, k, s=1.001, tol=1e-8, flexible=flexible)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, lo, hi, 1.001, prec, block_size=3) as h:
+        x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
+        st = pc.pcg_solve(h, _t(b), x, tol=1e-8, flexible=flexible)
+    assert st["status"] == "OK" and abs(st["iters"] - ref.iters) <= 2, (st, ref.iters)
+    assert rel_inf(x.cpu().numpy(), ref.x_hat) <= 1e-6
+    assert st["relres_true"] <= TRUE_RES
+
+
+def test_second_level_lanczos_and_pattern_check(pc):
+    """Lanczos on W^T A W matches the oracle's; a CSR matrix whose node rows differ in pattern
+    (the 7-point Laplacian numbered point by point) is rejected for block size 3."""
+    c = case("csr_el")
+    v0 = W.uniform(7, c.n, 0.5, 1.5)
+    _, _, _, cm = oracle.second_level_operator(c.rp, c.ci, c.v)
+    lo_ref, hi_ref = oracle.lanczos_extremes(lambda x: cm @ x, v0, 30)
+    lo, hi = pc.pcheb_estimate_bounds(c.operator(torch, DEV), _t(v0), 30, block_size=3)
+    assert abs(lo - lo_ref) <= 1e-9 * lo_ref and abs(hi - hi_ref) <= 1e-9 * hi_ref, (lo, lo_ref, hi, hi_ref)
+    c7 = case("csr7")
+    assert c7.n % 3 == 0
+    with pytest.raises(RuntimeError, match="pattern"):
+        pc.pcheb_setup(c7.operator(torch, DEV), 5, 0.01, 2.0, 1.001, "f64", block_size=3)
+    with pytest.raises(RuntimeError, match="pattern"):
+        pc.pcheb_estimate_bounds(c7.operator(torch, DEV), _t(W.uniform(7, c7.n, 0.5, 1.5)), 10, block_size=3)
+
+
 def newton_ref(c, r, nlev, s=1.001):
     """D^-1/2 P_nlev(A) D^-1/2 r by the oracle's recursion of Alg. 1."""
     a, d = oracle.jacobi_scale(oracle.csr(c.rp, c.ci, c.v))
