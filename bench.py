@@ -406,7 +406,9 @@ def run_c3(torch, pc, W, dev):
 
 def run_c4(torch, pc, W, dev):
     """Q1 elasticity 128^3 x 3 (502M nonzeros): F32 recurrence with k in {20, 60} stored as CSR and
-    as SELL-C-sigma (C = 64, sigma = 256), FP64 flexible PCG; FP64 plain PCG (k = 0) beside."""
+    as SELL-C-sigma (C = 64, sigma = 256), FP64 flexible PCG; FP64 plain PCG (k = 0) beside.  Also the
+    second-level preconditioner on the 3x3 node-block Jacobi factor (block_size 3, SELL, bounds of
+    W^T A W by Lanczos(30) x1.01): block Jacobi PCG (k = 0) and k = 20."""
     N = 128
     rp, ci, v = W.elasticity_q1_csr(N, seed=2)
     n = len(rp) - 1
@@ -420,8 +422,19 @@ def run_c4(torch, pc, W, dev):
     pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
     lo, hi = pc.pcheb_estimate_bounds(pc.Operator.csr(*d), v0, 30)
     hi *= 1.01
+    lo3, hi3 = pc.pcheb_estimate_bounds(pc.Operator.csr(*d), v0, 30, block_size=3)
+    hi3 *= 1.01
     del v0
     rows = []
+    op = pc.Operator.csr(*d, sell=True, sigma=256)
+    for k, prec in ((0, "f64"), (20, "f32")):
+        with pc.pcheb_setup(op, k, lo3, hi3, 1.001, prec, block_size=3) as h:
+            st, x, lat = _timed_solves(torch, pc, h, b, 1, prec != "f64", time_kernels=k >= 3)
+        row = {"format": "sell256", "block_size": 3, "k": k, "prec": prec, "iters": st["iters"],
+               "solve_s": round(lat[0], 3), "relres_true": st["relres_true"],
+               "err_vs_xstar": float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))}
+        rows.append(row)
+        log(f"  c4 {row}")
     for fmt in ("sell256", "csr"):
         op = pc.Operator.csr(*d, sell=fmt != "csr", sigma=256)
         cases = [(0, "f64"), (20, "f32"), (60, "f32")] if fmt == "sell256" else [(20, "f32"), (60, "f32")]
@@ -439,7 +452,8 @@ def run_c4(torch, pc, W, dev):
             log(f"  c4 {row}")
     print(json.dumps({"config": "c4", "workload": "Q1 elasticity 128^3 free nodes x 3, E = 1 +- 10% seed 2, nu 0.3, "
                       "Lanczos(30) bounds x1.01, b = A x*, tol 1e-8", "n": n, "nnz": nnz, "lambda_min": lo,
-                      "lambda_max": hi, "rows": rows}), flush=True)
+                      "lambda_max": hi, "block3_lambda_min": lo3, "block3_lambda_max": hi3, "rows": rows}),
+          flush=True)
 
 
 PD_POWER_STEPS = 300  # power steps for lambda_max (30 land 2.6% low on 256^3, 300 within 0.3%)

@@ -65,8 +65,7 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       break;
     }
     case PCHEB_OP_CSR: {
-      const int rows = kBlock / h.lanes;
-      const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);
+      const uint64_t tiles = uint64_t((h.n + kBlock - 1) / kBlock);
       grid = round_grid(tiles);
 #define PCHEB_CSR_CASE(L)                                                                              \
   case L:                                                                                              \

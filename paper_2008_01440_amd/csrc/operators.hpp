@@ -342,7 +342,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h_lo(In in, Epi epi, const 
 //
 // LANES consecutive lanes share one row (LANES = 8 for ~7 nonzeros per row,
 // 32 for ~80), read its nonzeros with unit stride and combine them with a
-// butterfly inside the group.  A tile is kBlock / LANES consecutive rows.
+// butterfly inside the group.  A wavefront owns 64 consecutive rows and walks
+// them in LANES passes of 64 / LANES rows; after each pass lane L picks up the
+// sum of row L from its group, so the epilogue runs once per wavefront with
+// all 64 lanes on consecutive rows (unit-stride vector accesses) instead of
+// with one lane per group.  A tile is the kBlock rows of a block.
 template <int LANES, class Tv, class In, class Epi>
 __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                 const Tv* __restrict__ val, In in, Epi epi, int64_t n,
@@ -353,19 +357,30 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
-  constexpr int kRows = kBlock / LANES;
-  const int g = threadIdx.x % LANES;
+  constexpr int kGroups = kWave / LANES;  // rows of one pass
+  const int lane = int(threadIdx.x) % kWave;
+  const int wave = int(threadIdx.x) / kWave;
+  const int g = lane % LANES;
+  const int grp = lane / LANES;
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
-    const int64_t row = int64_t(t) * kRows + threadIdx.x / LANES;
-    acc sum = acc(0);
-    if (row < n) {
-      const int32_t b = rowptr[row], e = rowptr[row + 1];
+    const int64_t base = (int64_t(t) * (kBlock / kWave) + wave) * kWave;  // first row of the wavefront
+    if (base >= n) continue;
+    const int64_t myrow = base + lane;
+    const int32_t rb_lane = rowptr[myrow < n ? myrow : n];
+    const int32_t re_lane = rowptr[myrow + 1 < n ? myrow + 1 : n];
+    acc mine = acc(0);
+    for (int it = 0; it < LANES; ++it) {
+      const int r = it * kGroups + grp;  // row of this group in this pass (rows past n are empty)
+      const int32_t b = __shfl(rb_lane, r, kWave), e = __shfl(re_lane, r, kWave);
+      acc sum = acc(0);
       for (int32_t j = b + g; j < e; j += LANES) sum += acc(Store<Tv>::ld(val, j)) * in.ld(col[j]);
-    }
 #pragma unroll
-    for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-    if (row < n && g == 0) epi(row, in.ld(row), sum, epi.load(row), part);
+      for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+      const acc v = __shfl(sum, (lane % kGroups) * LANES, kWave);  // row it * kGroups + lane % kGroups
+      if (lane / kGroups == it) mine = v;
+    }
+    if (myrow < n) epi(myrow, in.ld(myrow), mine, epi.load(myrow), part);
   }
   finish_reduction(epi, part, rb, slot);
 }
