@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h_lo(In in, Epi epi, const 
 
 // ------------------------------------------------------------------ CSR
 //
-// LANES consecutive lanes share one row (LANES = 8 for ~7 nonzeros per row,
+// LANES consecutive lanes share one row (LANES = 4 for ~7 nonzeros per row,
 // 32 for ~80), read its nonzeros with unit stride and combine them with a
 // butterfly inside the group.  A wavefront owns 64 consecutive rows and walks
 // them in LANES passes of 64 / LANES rows; after each pass lane L picks up the
