@@ -138,17 +138,20 @@ struct EpiChebLast {
   }
 };
 
-// q = A p for the search direction p: stores q and reduces (p, q).  The last
+// q = A p for the search direction p: stores q (and p when p_new is set, the
+// input functor having formed p = z + beta p_old) and reduces (p, q).  The last
 // block sets alpha = gamma / (p, q) or flags a breakdown when (p, q) <= 0.
 struct EpiDirection {
   using acc = double;
   static constexpr int NV = 1;
   static constexpr bool reduce = true;
+  double* p_new;  // may be null
   double* q;
   DevState* st;
   const DevState* guard;
   int64_t ld;
   __device__ __forceinline__ void bind(int slot) {
+    if (p_new) p_new += slot * ld;
     q += slot * ld;
     st += slot;
     if (guard) guard += slot;
@@ -157,6 +160,7 @@ struct EpiDirection {
   using Pre = NoPre;
   __device__ __forceinline__ Pre load(int64_t) const { return {}; }
   __device__ __forceinline__ void operator()(int64_t i, double p, double ap, const Pre&, double (&part)[NV]) const {
+    if (p_new) p_new[i] = p;
     q[i] = ap;
     part[0] += p * ap;
   }

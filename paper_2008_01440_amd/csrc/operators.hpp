@@ -438,6 +438,25 @@ struct InVec {
   __device__ __forceinline__ acc ld(int64_t i) const { return Store<T>::ld(p, i); }
 };
 
+// p = z + beta * p_old, formed where it is read (beta from the solver state).
+// The 7-point kernel calls ld once per point of a tile plane and its halo.
+struct InDirection {
+  using acc = double;
+  static constexpr bool narrow = false;
+  const double* z;
+  const double* p_old;
+  const DevState* st;
+  double beta;
+  int64_t stride;
+  __device__ __forceinline__ void bind(int slot) {
+    z += slot * stride;
+    p_old += slot * stride;
+    st += slot;
+  }
+  __device__ __forceinline__ void prepare() { beta = st->beta; }
+  __device__ __forceinline__ double ld(int64_t i) const { return z[i] + beta * p_old[i]; }
+};
+
 // v scaled by D^-1/2 (for the symmetric scaled operator of the Lanczos estimator).
 struct InScaled {
   using acc = double;

@@ -370,9 +370,10 @@ __global__ void k_start_zero(const double* b, int64_t ldb, double* x, int64_t ld
   block_partial<2>(part, rb, slot);
 }
 
-// Search direction p = z + beta p_old, beta from the slot's state.  A pass of
-// its own: forming p inside the stencil kernel would load z and p_old for
-// every neighbour, and that kernel is bound by the issue of its loads.
+// Search direction p = z + beta p_old, beta from the slot's state: a pass of
+// its own for the operators whose kernels read an input value more than once
+// (CSR and SELL gathers, the 27-point stencil); the 7-point kernel forms p as
+// it stages each plane.
 __global__ void k_direction(const double* z, const double* p_old, double* p, int64_t ldw, int64_t n,
                             const DevState* st, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
@@ -1120,8 +1121,14 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
   double* p_new = h.p[cur ^ 1];
   const uint32_t g = pair_grid(n);
   const dim3 grid(g, sl.count);
-  k_direction<<<grid, kBlock, 0, s>>>(h.z, h.p[cur], p_new, h.ldw, n, st, sl.first);
-  launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{h.q, st, st, h.ldw}, sl.first, sl.count, s);
+  if (h.op.kind == PCHEB_OP_STENCIL7) {
+    // the 7-point kernel reads each input point once: form p there and store it beside q
+    launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0, h.ldw}, EpiDirection{p_new, h.q, st, st, h.ldw}, sl.first,
+                sl.count, s);
+  } else {
+    k_direction<<<grid, kBlock, 0, s>>>(h.z, h.p[cur], p_new, h.ldw, n, st, sl.first);
+    launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{nullptr, h.q, st, st, h.ldw}, sl.first, sl.count, s);
+  }
   if (refresh) {
     k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
