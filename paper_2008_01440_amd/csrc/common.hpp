@@ -157,21 +157,33 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], ReduceBuf rb, int
 }
 
 // One block per solve slot (slot = slot0 + blockIdx.x); fin.bind(slot) points
-// the functor at that slot's state before fin(total).
+// the functor at that slot's state before fin(total).  kFinThreads threads each
+// load their kMaxGrid / kFinThreads partials up front (one memory latency, not
+// one per partial) and add them in block order.
+constexpr int kFinThreads = 1024;
+static_assert(kMaxGrid % kFinThreads == 0, "the finalize loads kMaxGrid / kFinThreads partials per thread");
 template <int NV, class Fin>
-__global__ __launch_bounds__(kBlock) void k_finalize(Fin fin, ReduceBuf rb, uint32_t nblocks, const DevState* guard,
-                                                     int slot0) {
+__global__ __launch_bounds__(kFinThreads) void k_finalize(Fin fin, ReduceBuf rb, uint32_t nblocks,
+                                                          const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.x);
   if (guard && guard[slot].done != kRunning) return;
   fin.bind(slot);
+  constexpr int kPer = kMaxGrid / kFinThreads;
+  double v[kPer][NV];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const uint32_t b = threadIdx.x + uint32_t(m) * kFinThreads;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[m][i] = b < nblocks ? rb.partials[partial_index(slot, b) + i] : 0.0;
+  }
   double acc[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) {
+  for (int i = 0; i < NV; ++i) {
+    acc[i] = 0.0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += rb.partials[partial_index(slot, b) + i];
+    for (int m = 0; m < kPer; ++m) acc[i] += v[m][i];
   }
-  block_sum<NV>(acc, threadIdx.x);
+  block_sum<NV, kFinThreads>(acc, threadIdx.x);
   if (threadIdx.x == 0) fin(acc);
 }
 

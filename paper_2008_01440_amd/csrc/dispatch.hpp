@@ -95,7 +95,7 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       fail(PCHEB_INVALID, "unknown operator kind");
   }
   if constexpr (Epi::reduce) {
-    k_finalize<Epi::NV, EpiFin<Epi>><<<nslots, kBlock, 0, s>>>(EpiFin<Epi>{epi}, h.rb(), grid, epi.guard, slot0);
+    k_finalize<Epi::NV, EpiFin<Epi>><<<nslots, kFinThreads, 0, s>>>(EpiFin<Epi>{epi}, h.rb(), grid, epi.guard, slot0);
   }
 }
 

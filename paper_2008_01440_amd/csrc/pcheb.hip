@@ -792,7 +792,7 @@ static void enqueue_newton(Handle& h, Slots sl, double* z, int64_t ldz, const do
   const uint32_t g = flat_grid(n);
   k_nt_final<T><<<dim3(g, sl.count), kBlock, 0, s>>>(t1, w, h.ldw, h.zeta[size_t(L)], z, ldz, r, ldr, q, n, guard,
                                                      h.rb(), dots ? 1 : 0, flexible, sl.first);
-  if (dots) k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, guard, sl.first);
+  if (dots) k_finalize<2, FinBeta><<<sl.count, kFinThreads, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, guard, sl.first);
 }
 
 #define PCHEB_BY_PREC(h, FN, ...)                      \
@@ -1078,13 +1078,13 @@ static void enqueue_precond(Handle& h, Slots sl, int init, int flexible, StepTim
       const uint32_t g = flat_grid(n / 3);
       k_node_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, h.binv, 1.0 / h.theta, n / 3,
                                                           h.st, h.rb(), 1, flexible, sl.first);
-      k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
+      k_finalize<2, FinBeta><<<sl.count, kFinThreads, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
       return;
     }
     const uint32_t g = pair_grid(n);
     k_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, invdiag(h), 1.0 / h.theta, n, h.st,
                                                   h.rb(), 1, flexible, sl.first);
-    k_finalize<2, FinBeta><<<sl.count, kBlock, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
+    k_finalize<2, FinBeta><<<sl.count, kFinThreads, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
     return;
   }
   enqueue_prep<T>(h, sl, h.r, h.ldw, h.st, s);
@@ -1106,7 +1106,7 @@ static void enqueue_start(Handle& h, Slots sl, const double* b, int64_t ldb, dou
     const uint32_t g = pair_grid(n);
     k_start_zero<<<dim3(g, sl.count), kBlock, 0, s>>>(b, ldb, x, ldx, h.r, h.p[0], h.ldw, invdiag(h), n, h.rb(),
                                                       sl.first);
-    k_finalize<2, FinStart><<<sl.count, kBlock, 0, s>>>(FinStart{h.st}, h.rb(), g, nullptr, sl.first);
+    k_finalize<2, FinStart><<<sl.count, kFinThreads, 0, s>>>(FinStart{h.st}, h.rb(), g, nullptr, sl.first);
   }
   enqueue_precond<T>(h, sl, 1, flexible, timer, s);
 }
@@ -1132,7 +1132,7 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
   if (refresh) {
     k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<2>><<<sl.count, kBlock, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
+    k_finalize<3, FinUpdate<2>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
     launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, h.r, invdiag(h), st, st, 2, ldb, h.ldw}, sl.first, sl.count,
                 s);
     enqueue_precond<T>(h, sl, 0, flexible, timer, s);
@@ -1141,17 +1141,17 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
   if (h.bs == 3) {  // node blocks: the preconditioner input needs whole nodes, so it is a pass of its own
     k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<2>><<<sl.count, kBlock, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
+    k_finalize<3, FinUpdate<2>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
     enqueue_precond<T>(h, sl, 0, flexible, timer, s);
   } else if (h.prm.k == 0) {
     k_update<double, 1><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, h.z,
                                                 1.0 / h.theta, n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<1>><<<sl.count, kBlock, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st, sl.first);
+    k_finalize<3, FinUpdate<1>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st, sl.first);
   } else {
     k_update<T, 0><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), reinterpret_cast<T*>(h.s),
                                            reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb(),
                                            sl.first);
-    k_finalize<3, FinUpdate<0>><<<sl.count, kBlock, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st, sl.first);
+    k_finalize<3, FinUpdate<0>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st, sl.first);
     if (h.prm.form == PCHEB_FORM_NEWTON)
       enqueue_newton<T>(h, sl, h.z, h.ldw, h.r, h.ldw, h.q, true, 0, flexible, st, s);
     else
