@@ -114,25 +114,32 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(const double* __restrict__
   }
 }
 
-// One block: out[col0 + k] = sum over blocks of partial[k][.] (each thread a
-// strided share in block order, then the fixed block tree), k < ncol.  With
+// Block k < ncol: out[col0 + k] = sum over blocks of partial[k][.] (each thread
+// a strided share in block order, then the fixed block tree).  With
 // `alpha`, the sum of column j (the step) is also stored in alpha[j].  With
 // `norm`, column 0 is a squared norm: *norm = its square root and *inv = 1 / *norm.
-__global__ __launch_bounds__(kBlock) void k_lz_finalize(const double* __restrict__ partial, int ncol, double* out,
-                                                        int col0, double* alpha, int j, double* norm,
-                                                        double* inv) {
-  for (int k = 0; k < ncol; ++k) {
-    double t[1] = {0.0};
-    for (int b = threadIdx.x; b < kLzGrid; b += blockDim.x) t[0] += partial[k * kLzGrid + b];
-    block_sum<1>(t, threadIdx.x);
-    if (threadIdx.x == 0) {
-      if (out) out[col0 + k] = t[0];
-      if (alpha && col0 + k == j) alpha[j] = t[0];
-      if (norm && k == 0) {
-        const double r = sqrt(t[0]);
-        norm[0] = r;
-        inv[0] = 1.0 / r;
-      }
+__global__ __launch_bounds__(kFinThreads) void k_lz_finalize(const double* __restrict__ partial, int ncol,
+                                                             double* out, int col0, double* alpha, int j,
+                                                             double* norm, double* inv) {
+  // every thread loads its partials before adding them
+  static_assert(kLzGrid % kFinThreads == 0, "partials per thread");
+  constexpr int kPer = kLzGrid / kFinThreads;
+  const int k = int(blockIdx.x);
+  if (k >= ncol) return;
+  double v[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) v[m] = partial[k * kLzGrid + int(threadIdx.x) + m * kFinThreads];
+  double t[1] = {0.0};
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) t[0] += v[m];
+  block_sum<1, kFinThreads>(t, threadIdx.x);
+  if (threadIdx.x == 0) {
+    if (out) out[col0 + k] = t[0];
+    if (alpha && col0 + k == j) alpha[j] = t[0];
+    if (norm && k == 0) {
+      const double r = sqrt(t[0]);
+      norm[0] = r;
+      inv[0] = 1.0 / r;
     }
   }
 }
@@ -246,7 +253,7 @@ static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double
 
   // v_0 = v0 / ||v0|| (the one host check: a zero or non-finite start vector is an error)
   k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(v0, 0, 0, 1, v0, n, partial);
-  k_lz_finalize<<<1, kBlock, 0, s>>>(partial, 1, nullptr, 0, nullptr, 0, nrm0, inv);
+  k_lz_finalize<<<1, kFinThreads, 0, s>>>(partial, 1, nullptr, 0, nullptr, 0, nrm0, inv);
   double nrm = 0.0;
   PCHEB_HIP_CHECK(hipMemcpyAsync(&nrm, nrm0, sizeof(double), hipMemcpyDeviceToHost, s));
   PCHEB_HIP_CHECK(hipStreamSynchronize(s));
@@ -261,22 +268,22 @@ static void lanczos(Handle& h, const double* v0, int steps, double* lmin, double
     for (int c0 = 0; c0 < cols; c0 += kCols) {
       const int nc = std::min(kCols, cols - c0);
       k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(V, ldv, c0, nc, w, n, partial);
-      k_lz_finalize<<<1, kBlock, 0, s>>>(partial, nc, coef, c0, alpha, j, nullptr, nullptr);
+      k_lz_finalize<<<nc, kFinThreads, 0, s>>>(partial, nc, coef, c0, alpha, j, nullptr, nullptr);
     }
     if (cols <= kCols) {  // first update fused with the second pass's dot products
       k_lz_update<true, false><<<kLzGrid, kBlock, 0, s>>>(V, ldv, cols, coef, w, n, partial);
-      k_lz_finalize<<<1, kBlock, 0, s>>>(partial, cols, coef, 0, nullptr, j, nullptr, nullptr);
+      k_lz_finalize<<<cols, kFinThreads, 0, s>>>(partial, cols, coef, 0, nullptr, j, nullptr, nullptr);
     } else {
       k_lz_update<false, false><<<kLzGrid, kBlock, 0, s>>>(V, ldv, cols, coef, w, n, partial);
       for (int c0 = 0; c0 < cols; c0 += kCols) {
         const int nc = std::min(kCols, cols - c0);
         k_lz_dots<<<kLzGrid, kBlock, 0, s>>>(V, ldv, c0, nc, w, n, partial);
-        k_lz_finalize<<<1, kBlock, 0, s>>>(partial, nc, coef, c0, nullptr, j, nullptr, nullptr);
+        k_lz_finalize<<<nc, kFinThreads, 0, s>>>(partial, nc, coef, c0, nullptr, j, nullptr, nullptr);
       }
     }
     // pass 2 update with the norm: beta_j = ||w||
     k_lz_update<false, true><<<kLzGrid, kBlock, 0, s>>>(V, ldv, cols, coef, w, n, partial);
-    k_lz_finalize<<<1, kBlock, 0, s>>>(partial, 1, nullptr, 0, nullptr, j, beta + j, inv);
+    k_lz_finalize<<<1, kFinThreads, 0, s>>>(partial, 1, nullptr, 0, nullptr, j, beta + j, inv);
     if (j + 1 < m) k_lz_scale<<<g, kBlock, 0, s>>>(w, V + int64_t(j + 1) * ldv, inv, n);
     PCHEB_HIP_CHECK(hipGetLastError());
   }
