@@ -159,9 +159,13 @@ typedef struct pcheb_handle_s* pcheb_handle;
  * rho_0 = 1/sigma, rho_j = 1/(2 sigma - rho_{j-1}) (eq. rhocheb), the
  * reduced-precision and SELL copies the library owns, and the workspace for
  * one right-hand side.  Synchronises `stream` once.
+ * With block_size 3 it also factors the 3x3 diagonal block of every node
+ * (second-level preconditioner, see pcheb_params).
  * Errors: INVALID (k out of range, lambda_min <= 0, lambda_min >= lambda_max,
- * s < 1, null or inconsistent arrays, unsupported SELL chunk), NOT_SPD
- * (diagonal <= 0 or a coefficient <= 0), OOM, HIP.  *out is set only on OK.
+ * s < 1, null or inconsistent arrays, unsupported SELL chunk, block_size not
+ * 1 or 3, block_size 3 on a stencil, with n % 3 != 0 or with node rows of
+ * different patterns), NOT_SPD (diagonal <= 0, a coefficient <= 0, or a node
+ * block that is not positive definite), OOM, HIP.  *out is set only on OK.
  */
 pcheb_status pcheb_setup(const pcheb_operator* A, const pcheb_params* p, hipStream_t stream,
                          pcheb_handle* out);
@@ -169,7 +173,9 @@ pcheb_status pcheb_setup(const pcheb_operator* A, const pcheb_params* p, hipStre
 /*
  * z = D^-1/2 p_k(A) D^-1/2 r = p_k(D^-1 A_hat) D^-1 r: the preconditioner for
  * the unscaled system, by Alg. 2 (step j uses rho_j and rho_{j-1}, matching
- * the p_k recurrence of Sec. 3).  r and z are device float64 arrays of
+ * the p_k recurrence of Sec. 3), or by Alg. 1 for the Newton form.  With
+ * block_size 3, z = p_k(B^-1 A_hat) B^-1 r with B the node blocks, which is
+ * W p_k(W^T A W) W^T r on the scaled system.  r and z are device float64 arrays of
  * nrhs vectors with leading dimension ld; z must not overlap r.  Enqueued on
  * `stream` without host synchronisation.  Errors: INVALID, HIP, OOM.
  */
