@@ -9,15 +9,14 @@
 
 namespace pcheb {
 
-constexpr int kZChunk = 8;  // planes marched per 27-point stencil tile (64 x 4 columns)
 #ifndef PCHEB_ST7_TY
 #define PCHEB_ST7_TY 4
 #endif
 #ifndef PCHEB_ST7_ZC
 #define PCHEB_ST7_ZC 16
 #endif
-constexpr int kSt7Rows = PCHEB_ST7_TY;    // grid rows per 7-point tile (waves per block)
-constexpr int kSt7ZChunk = PCHEB_ST7_ZC;  // planes marched per 7-point tile
+constexpr int kSt7Rows = PCHEB_ST7_TY;    // grid rows per stencil tile (waves per block), 7- and 27-point
+constexpr int kSt7ZChunk = PCHEB_ST7_ZC;  // planes marched per stencil tile
 
 struct StencilGrid {
   uint32_t tiles_x, tiles_y, ntiles, grid;
@@ -51,17 +50,12 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       break;
     }
     case PCHEB_OP_STENCIL27H: {
-      const StencilGrid g = stencil_grid(op, 4, kZChunk);
+      const StencilGrid g = stencil_grid(op, kSt7Rows, kSt7ZChunk);
       grid = g.grid;
-      if constexpr (sizeof(acc) == 8) {
-        k_stencil27h<SCALED, kZChunk, acc, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
-            in, epi, reinterpret_cast<const acc*>(op.cell_coeff), op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y,
-            g.ntiles, h.rb(), slot0);
-      } else {
-        static_assert(SCALED || sizeof(acc) == 8, "float arithmetic is used for D^-1 A_hat only");
-        k_stencil27h_lo<kZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, 4), 0, s>>>(
-            in, epi, h.rho_lo, h.invd_lo, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
-      }
+      const acc* rho = sizeof(acc) == 8 ? reinterpret_cast<const acc*>(h.rho64) : reinterpret_cast<const acc*>(h.rho_lo);
+      const acc* invd = sizeof(acc) == 8 ? reinterpret_cast<const acc*>(h.invd) : reinterpret_cast<const acc*>(h.invd_lo);
+      k_stencil27h_lds<SCALED, kSt7Rows, kSt7ZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, kSt7Rows), 0, s>>>(
+          in, epi, rho, invd, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_CSR: {

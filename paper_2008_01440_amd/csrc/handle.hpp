@@ -55,6 +55,7 @@ struct Handle {
   double* sell_aval = nullptr;  // A_hat values (float64)
   void* sell_bval = nullptr;    // D^-1 A_hat values (storage precision)
   int32_t* sell_perm = nullptr; // null when sigma == 1
+  double* rho64 = nullptr;      // STENCIL27H: 1 / (2 kappa) per cell (double products)
   float* rho_lo = nullptr;      // STENCIL27H, float recurrences: 1 / (2 kappa) per cell
   float* invd_lo = nullptr;     // STENCIL27H, float recurrences: D^-1 rounded to float
   int bs = 1;                   // first-level block size (1: Jacobi scaling, 3: node blocks)

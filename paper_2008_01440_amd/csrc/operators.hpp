@@ -161,168 +161,141 @@ __global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, in
 
 // ------------------------------------------------------------------ 27-point harmonic stencil
 //
-// Face weights are harmonic means 2 a b / (a + b) of the cell coefficients,
-// recomputed at every product (this kernel runs in double arithmetic; the
-// float recurrences use k_stencil27h_lo below).
-//
-// Same tiling as the 7-point kernel.  Each thread keeps the 3x3 neighbourhood
-// of y and of the cell coefficients for the planes z-1, z, z+1 in registers
-// and loads one new 3x3 plane per step.  A coefficient of 0 marks a cell
-// outside the grid (a zero-Dirichlet ghost that adds k_i to the diagonal).
-template <bool SCALED, int ZC, class KT, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_stencil27h(In in, Epi epi, const KT* __restrict__ kappa, int nx,
-                                                       int ny, int nz, uint32_t tiles_x, uint32_t tiles_y,
-                                                       uint32_t ntiles, ReduceBuf rb, int slot0) {
+// Tiles and planes as in k_stencil7: a block of 64 x TY threads owns 64 x TY
+// columns, marches ZC planes, and stages each incoming plane of y and of
+// rho = 1 / (2 kappa) with its one-point halo (corners included) in LDS, two
+// buffers and one barrier per plane.  Each thread copies its 3 x 3
+// neighbourhood of the staged plane into a register ring of three planes, so
+// a point's 26 neighbours cost 18 LDS reads per plane instead of 18 loads.
+// The face weight 2 k_i k_n / (k_i + k_n) is 1 / (rho_i + rho_n): one add and
+// a float hardware reciprocal (float arithmetic) or an IEEE division (double).
+// Cells outside the grid read y = 0 and rho = +inf (weight exactly 0); their
+// Dirichlet ghost contributions are in the stored D^-1 (invd), so
+//   SCALED:  m = y_i - invd_i * sum_n w_in y_n      (D^-1 A_hat y)
+//   else:    m = y_i / invd_i - sum_n w_in y_n      (A_hat y, double only).
+// The neighbour sum runs over dz, dy, dx in order.
+template <bool SCALED, int TY, int ZC, class In, class Epi>
+__global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
+                                                            const typename Epi::acc* __restrict__ rho,
+                                                            const typename Epi::acc* __restrict__ invd, int nx,
+                                                            int ny, int nz, uint32_t tiles_x, uint32_t tiles_y,
+                                                            uint32_t ntiles, ReduceBuf rb, int slot0) {
+  static_assert(TY >= 2 && 2 * (TY + 2) <= 64, "halo loads need two waves and at most 64 side points");
   using acc = typename Epi::acc;
+  static_assert(SCALED || sizeof(acc) == 8, "A_hat products run in double");
+  constexpr int W = 64 + 2;
+  __shared__ acc ys[2][TY + 2][W];
+  __shared__ acc rs[2][TY + 2][W];
   const int slot = slot0 + int(blockIdx.y);
   if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
   const int64_t plane = int64_t(nx) * ny;
+  const int tx = int(threadIdx.x), ty = int(threadIdx.y);
+  const acc kInf = acc(__builtin_inf());
+  auto ldy = [&](bool ok, int64_t j) {
+    if constexpr (In::narrow) {  // as in k_stencil7: no branch around narrow loads
+      const acc v = acc(in.ld(ok ? j : 0));
+      return ok ? v : acc(0);
+    } else {
+      return ok ? acc(in.ld(j)) : acc(0);
+    }
+  };
+  auto ldr = [&](bool ok, int64_t j) { return ok ? rho[j] : kInf; };
+  const bool hy_on = ty == 0 || ty == TY - 1;  // a halo row point: row y0 - 1 or y0 + TY
+  const int hy_row = ty == 0 ? 0 : TY + 1;
+  const bool hx_on = ty == 1 && tx < 2 * (TY + 2);  // a halo side point (corners included)
+  const int hx_r = tx >> 1, hx_col = (tx & 1) ? W - 1 : 0;
+  uint32_t k = 0;  // planes staged so far: buffer k & 1
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
-    const uint32_t tx = t % tiles_x;
+    const uint32_t tix = t % tiles_x;
     const uint32_t rest = t / tiles_x;
-    const uint32_t ty = rest % tiles_y;
-    const uint32_t tz = rest / tiles_y;
-    const int x = int(tx) * 64 + int(threadIdx.x);
-    const int y = int(ty) * 4 + int(threadIdx.y);
-    const int z0 = int(tz) * ZC;
-    if (x >= nx || y >= ny) continue;
+    const int x0 = int(tix) * 64;
+    const int y0 = int(rest % tiles_y) * TY;
+    const int z0 = int(rest / tiles_y) * ZC;
     const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
-    acc yv[3][3][3];
-    acc kv[3][3][3];
-    auto load_plane = [&](int slot, int zz) {
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = x + dx, yy = y + dy;
-          const bool ok = zz >= 0 && zz < nz && xx >= 0 && xx < nx && yy >= 0 && yy < ny;
-          const int64_t j = ok ? xx + int64_t(nx) * yy + plane * zz : x + int64_t(nx) * y;  // clamped, then zeroed
-          const acc yj = in.ld(j);
-          const acc kj = acc(kappa[j]);
-          yv[slot][dy + 1][dx + 1] = ok ? yj : acc(0);
-          kv[slot][dy + 1][dx + 1] = ok ? kj : acc(0);
-        }
-      }
+    const int x = x0 + tx, y = y0 + ty;
+    const bool own = x < nx && y < ny;
+    const int64_t i0 = x + int64_t(nx) * y;
+    const int hy_y = ty == 0 ? y0 - 1 : y0 + TY;
+    const bool hy_ok = hy_on && x < nx && hy_y >= 0 && hy_y < ny;
+    const int64_t hy_i = x + int64_t(nx) * hy_y;
+    const int hx_x = (tx & 1) ? x0 + 64 : x0 - 1, hx_y = y0 - 1 + hx_r;
+    const bool hx_ok = hx_on && hx_x >= 0 && hx_x < nx && hx_y >= 0 && hx_y < ny;
+    const int64_t hx_i = hx_x + int64_t(nx) * hx_y;
+    // y and rho of plane zz at this thread's LDS entries (own, halo row, halo side)
+    struct Vals {
+      acc y0, r0, y1, r1, y2, r2;
     };
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
-    for (int z = z0; z < z1; ++z) {
-      load_plane(2, z + 1);
-      const acc ki = kv[1][1][1];
-      acc diag = acc(0), off = acc(0);
-#pragma unroll
-      for (int dz = 0; dz < 3; ++dz) {
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-          for (int dx = 0; dx < 3; ++dx) {
-            if (dz == 1 && dy == 1 && dx == 1) continue;
-            const acc kn = kv[dz][dy][dx];
-            if (kn > acc(0)) {
-              const acc h = acc(2) * ki * kn / (ki + kn);
-              diag += h;
-              off += h * yv[dz][dy][dx];
-            } else {
-              diag += ki;
-            }
-          }
-        }
+    auto fetch = [&](int zz) {
+      const bool zok = zz >= 0 && zz < nz;
+      const int64_t pz = plane * zz;
+      return Vals{ldy(zok && own, i0 + pz),   ldr(zok && own, i0 + pz),   ldy(zok && hy_ok, hy_i + pz),
+                  ldr(zok && hy_ok, hy_i + pz), ldy(zok && hx_ok, hx_i + pz), ldr(zok && hx_ok, hx_i + pz)};
+    };
+    acc yv[3][3][3], rv[3][3][3];
+    auto stage = [&](const Vals& v, int ring) {
+      acc(*yb)[W] = ys[k & 1];
+      acc(*rb2)[W] = rs[k & 1];
+      yb[ty + 1][tx + 1] = v.y0;
+      rb2[ty + 1][tx + 1] = v.r0;
+      if (hy_on) {
+        yb[hy_row][tx + 1] = v.y1;
+        rb2[hy_row][tx + 1] = v.r1;
       }
-      const acc yc = yv[1][1][1];
-      const acc m = SCALED ? yc - off / diag : diag * yc - off;
-      const int64_t i = x + int64_t(nx) * y + plane * z;
-      epi(i, yc, m, epi.load(i), part);
+      if (hx_on) {
+        yb[hx_r][hx_col] = v.y2;
+        rb2[hx_r][hx_col] = v.r2;
+      }
+      __syncthreads();
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-          yv[0][dy][dx] = yv[1][dy][dx];
-          kv[0][dy][dx] = kv[1][dy][dx];
-          yv[1][dy][dx] = yv[2][dy][dx];
-          kv[1][dy][dx] = kv[2][dy][dx];
+          yv[ring][dy][dx] = yb[ty + dy][tx + dx];
+          rv[ring][dy][dx] = rb2[ty + dy][tx + dx];
         }
       }
-    }
-  }
-  finish_reduction(epi, part, rb, slot);
-}
-
-// D^-1 A_hat y in float arithmetic (the F32 / BF16 recurrences).  With
-// rho = 1 / (2 kappa) per cell the face weight is 1 / (rho_i + rho_n): one add
-// and one hardware reciprocal (about 1 ulp) per neighbour.  Cells outside the
-// grid read rho = +inf, so their weight is exactly 0 (a zero-Dirichlet ghost
-// contributes only to the diagonal), and the reciprocal of the diagonal is
-// precomputed from the float64 one, so no branches and no diagonal sum remain.
-template <int ZC, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_stencil27h_lo(In in, Epi epi, const float* __restrict__ rho,
-                                                          const float* __restrict__ invd, int nx, int ny, int nz,
-                                                          uint32_t tiles_x, uint32_t tiles_y, uint32_t ntiles,
-                                                          ReduceBuf rb, int slot0) {
-  static_assert(sizeof(typename Epi::acc) == 4, "float arithmetic only");
-  const int slot = slot0 + int(blockIdx.y);
-  if (bind_slot(in, epi, slot)) return;
-  double part[Epi::NV];
-#pragma unroll
-  for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
-  const int64_t plane = int64_t(nx) * ny;
-  XcdTiles tiles(ntiles);
-  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
-    const uint32_t tx = t % tiles_x;
-    const uint32_t rest = t / tiles_x;
-    const uint32_t ty = rest % tiles_y;
-    const uint32_t tz = rest / tiles_y;
-    const int x = int(tx) * 64 + int(threadIdx.x);
-    const int y = int(ty) * 4 + int(threadIdx.y);
-    const int z0 = int(tz) * ZC;
-    if (x >= nx || y >= ny) continue;
-    const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
-    float yv[3][3][3];
-    float rv[3][3][3];
-    auto load_plane = [&](int slot, int zz) {
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = x + dx, yy = y + dy;
-          const bool ok = zz >= 0 && zz < nz && xx >= 0 && xx < nx && yy >= 0 && yy < ny;
-          if constexpr (In::narrow) {  // as in k_stencil7: no branch around narrow loads
-            const int64_t j = ok ? xx + int64_t(nx) * yy + plane * zz : x + int64_t(nx) * y;
-            const float yj = float(in.ld(j));
-            const float rj = rho[j];
-            yv[slot][dy + 1][dx + 1] = ok ? yj : 0.0f;
-            rv[slot][dy + 1][dx + 1] = ok ? rj : __builtin_inff();
-          } else {
-            const int64_t j = xx + int64_t(nx) * yy + plane * zz;
-            yv[slot][dy + 1][dx + 1] = ok ? float(in.ld(j)) : 0.0f;
-            rv[slot][dy + 1][dx + 1] = ok ? rho[j] : __builtin_inff();
-          }
-        }
-      }
+      ++k;
     };
-    load_plane(0, z0 - 1);
-    load_plane(1, z0);
+    stage(fetch(z0 - 1), 0);
+    stage(fetch(z0), 1);
+    Vals nxt = fetch(z0 + 1);
+    typename Epi::Pre pre{};
+    if (own) pre = epi.load(i0 + plane * z0);
     for (int z = z0; z < z1; ++z) {
-      load_plane(2, z + 1);
-      const float ri = rv[1][1][1];
-      float off = 0.0f;
+      // the next plane's inputs and the next point's epilogue inputs, loaded a plane ahead
+      Vals after{acc(0), kInf, acc(0), kInf, acc(0), kInf};
+      typename Epi::Pre pre_next{};
+      if (z + 1 < z1) {
+        after = fetch(z + 2);
+        if (own) pre_next = epi.load(i0 + plane * (z + 1));
+      }
+      stage(nxt, 2);
+      if (own) {
+        const acc ri = rv[1][1][1];
+        acc off = acc(0);
 #pragma unroll
-      for (int dz = 0; dz < 3; ++dz) {
+        for (int dz = 0; dz < 3; ++dz) {
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
+          for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
-          for (int dx = 0; dx < 3; ++dx) {
-            if (dz == 1 && dy == 1 && dx == 1) continue;
-            off += __builtin_amdgcn_rcpf(ri + rv[dz][dy][dx]) * yv[dz][dy][dx];
+            for (int dx = 0; dx < 3; ++dx) {
+              if (dz == 1 && dy == 1 && dx == 1) continue;
+              if constexpr (sizeof(acc) == 4)
+                off += __builtin_amdgcn_rcpf(ri + rv[dz][dy][dx]) * yv[dz][dy][dx];
+              else
+                off += yv[dz][dy][dx] / (ri + rv[dz][dy][dx]);
+            }
           }
         }
+        const acc yc = yv[1][1][1];
+        const int64_t i = i0 + plane * z;
+        const acc m = SCALED ? yc - off * invd[i] : yc / invd[i] - off;
+        epi(i, yc, m, pre, part);
       }
-      const float yc = yv[1][1][1];
-      const int64_t i = x + int64_t(nx) * y + plane * z;
-      epi(i, yc, yc - off * invd[i], epi.load(i), part);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
@@ -333,9 +306,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil27h_lo(In in, Epi epi, const 
           rv[1][dy][dx] = rv[2][dy][dx];
         }
       }
+      nxt = after;
+      pre = pre_next;
     }
   }
-  finish_reduction(epi, part, rb, slot);
+  finish_reduction<Epi, 64 * TY>(epi, part, rb, slot);
 }
 
 // ------------------------------------------------------------------ CSR

@@ -144,6 +144,11 @@ __global__ void k_h27_invdiag(const double* kappa, int nx, int ny, int nz, doubl
   }
 }
 
+// rho = 1 / (2 kappa) per cell for the double 27-point products.
+__global__ void k_h27_rho64(const double* kappa, double* rho, int64_t n) {
+  GRID_STRIDE(i, n) rho[i] = 0.5 / kappa[i];
+}
+
 // Operator data of the float recurrences on the 27-point operator: rho = 1 / (2 kappa)
 // and D^-1, both rounded to float.
 __global__ void k_h27_lo(const double* kappa, const double* invd, float* rho, float* invd_lo, int64_t n) {
@@ -978,6 +983,8 @@ void setup_operator(Handle& h, hipStream_t s) {
   } else if (op.kind == PCHEB_OP_STENCIL27H) {
     h.invd = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
     k_h27_invdiag<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, op.nx, op.ny, op.nz, h.invd, bad);
+    h.rho64 = static_cast<double*>(dev_alloc(h, size_t(n) * sizeof(double)));
+    k_h27_rho64<<<flat_grid(n), kBlock, 0, s>>>(op.cell_coeff, h.rho64, n);
     if (h.prm.prec != PCHEB_F64) {
       h.rho_lo = static_cast<float*>(dev_alloc(h, size_t(n) * sizeof(float)));
       h.invd_lo = static_cast<float*>(dev_alloc(h, size_t(n) * sizeof(float)));
@@ -1040,7 +1047,7 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
     b += size_t(n) * 8 + size_t(chunks) * 12 + size_t(A->nnz) * (4 + 8 + e);
     if (A->sell_sigma > 1) b += size_t(n) * 4;
   }
-  if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 8 + (p->prec != PCHEB_F64 ? size_t(n) * 8 : 0);
+  if (A->kind == PCHEB_OP_STENCIL27H) b += size_t(n) * 16 + (p->prec != PCHEB_F64 ? size_t(n) * 8 : 0);
   if (p->block_size == 3) b += size_t(n / 3) * 12 * 8;  // node inverses and factors
   const int ny = (A->kind == PCHEB_OP_STENCIL7 && p->fuse_steps >= 2) ? 4 : 3;
   int nt = 0;  // Newton form: 2 nlev + 1 iterate vectors
