@@ -15,6 +15,7 @@ namespace pcheb {
 #ifndef PCHEB_ST7_ZC
 #define PCHEB_ST7_ZC 16
 #endif
+constexpr int64_t kCsrWideRows = int64_t(1) << 20;  // CSR: 64 rows per wavefront from this row count on
 constexpr int kSt7Rows = PCHEB_ST7_TY;    // grid rows per stencil tile (waves per block), 7- and 27-point
 constexpr int kSt7ZChunk = PCHEB_ST7_ZC;  // planes marched per stencil tile
 
@@ -59,13 +60,21 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       break;
     }
     case PCHEB_OP_CSR: {
-      const uint64_t tiles = uint64_t((h.n + kBlock - 1) / kBlock);
-      grid = round_grid(tiles);
-#define PCHEB_CSR_CASE(L)                                                                              \
-  case L:                                                                                              \
-    k_csr<L, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n,   \
-                                                               uint32_t(tiles), h.rb(), slot0);                \
-    break;
+      // 64 rows per wavefront for large matrices, 64 / lanes (one pass) for small ones
+      const bool wide = h.n >= kCsrWideRows;
+#define PCHEB_CSR_CASE(L)                                                                                  \
+  case L: {                                                                                                \
+    const int64_t rows = int64_t(kBlock / kWave) * (wide ? kWave : kWave / L);                             \
+    const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);                                              \
+    grid = round_grid(tiles);                                                                              \
+    if (wide)                                                                                              \
+      k_csr<L, L, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \
+                                                                     h.n, uint32_t(tiles), h.rb(), slot0); \
+    else                                                                                                   \
+      k_csr<L, 1, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \
+                                                                     h.n, uint32_t(tiles), h.rb(), slot0); \
+    break;                                                                                                 \
+  }
       switch (h.lanes) {
         PCHEB_CSR_CASE(4)
         PCHEB_CSR_CASE(8)

@@ -317,12 +317,15 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
 //
 // LANES consecutive lanes share one row (LANES = 4 for ~7 nonzeros per row,
 // 32 for ~80), read its nonzeros with unit stride and combine them with a
-// butterfly inside the group.  A wavefront owns 64 consecutive rows and walks
-// them in LANES passes of 64 / LANES rows; after each pass lane L picks up the
-// sum of row L from its group, so the epilogue runs once per wavefront with
-// all 64 lanes on consecutive rows (unit-stride vector accesses) instead of
-// with one lane per group.  A tile is the kBlock rows of a block.
-template <int LANES, class Tv, class In, class Epi>
+// butterfly inside the group.  A wavefront owns PASSES x 64 / LANES
+// consecutive rows and walks them in PASSES passes of 64 / LANES rows; after
+// each pass lane L picks up the sum of row L from its group, so the epilogue
+// runs once per wavefront on consecutive rows with unit-stride vector
+// accesses.  PASSES = LANES (64 rows per wavefront, every lane busy in the
+// epilogue) suits large matrices; PASSES = 1 keeps each wavefront's serial
+// chain short for small ones, where launch latency dominates.  A tile is the
+// rows of one block.
+template <int LANES, int PASSES, class Tv, class In, class Epi>
 __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                 const Tv* __restrict__ val, In in, Epi epi, int64_t n,
                                                 uint32_t ntiles, ReduceBuf rb, int slot0) {
@@ -333,19 +336,20 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
 #pragma unroll
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
   constexpr int kGroups = kWave / LANES;  // rows of one pass
+  constexpr int kRows = PASSES * kGroups;  // rows of one wavefront
   const int lane = int(threadIdx.x) % kWave;
   const int wave = int(threadIdx.x) / kWave;
   const int g = lane % LANES;
   const int grp = lane / LANES;
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
-    const int64_t base = (int64_t(t) * (kBlock / kWave) + wave) * kWave;  // first row of the wavefront
+    const int64_t base = (int64_t(t) * (kBlock / kWave) + wave) * kRows;  // first row of the wavefront
     if (base >= n) continue;
     const int64_t myrow = base + lane;
     const int32_t rb_lane = rowptr[myrow < n ? myrow : n];
     const int32_t re_lane = rowptr[myrow + 1 < n ? myrow + 1 : n];
     acc mine = acc(0);
-    for (int it = 0; it < LANES; ++it) {
+    for (int it = 0; it < PASSES; ++it) {
       const int r = it * kGroups + grp;  // row of this group in this pass (rows past n are empty)
       const int32_t b = __shfl(rb_lane, r, kWave), e = __shfl(re_lane, r, kWave);
       acc sum = acc(0);
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
       const acc v = __shfl(sum, (lane % kGroups) * LANES, kWave);  // row it * kGroups + lane % kGroups
       if (lane / kGroups == it) mine = v;
     }
-    if (myrow < n) epi(myrow, in.ld(myrow), mine, epi.load(myrow), part);
+    if (lane < kRows && myrow < n) epi(myrow, in.ld(myrow), mine, epi.load(myrow), part);
   }
   finish_reduction(epi, part, rb, slot);
 }
