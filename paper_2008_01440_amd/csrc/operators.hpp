@@ -168,9 +168,10 @@ __global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, in
 // neighbourhood of the staged plane into a register ring of three planes, so
 // a point's 26 neighbours cost 18 LDS reads per plane instead of 18 loads.
 // The face weight 2 k_i k_n / (k_i + k_n) is 1 / (rho_i + rho_n): one add and
-// a float hardware reciprocal (float arithmetic) or an IEEE division (double).
-// Cells outside the grid read y = 0 and rho = +inf (weight exactly 0); their
-// Dirichlet ghost contributions are in the stored D^-1 (invd), so
+// the hardware reciprocal, refined in double by one Newton-Raphson step
+// r <- r + r (1 - x r).  Cells outside the grid read y = 0 and rho = 1 (any
+// positive value: their weight multiplies y = 0); their Dirichlet ghost
+// contributions are in the stored D^-1 (invd), so
 //   SCALED:  m = y_i - invd_i * sum_n w_in y_n      (D^-1 A_hat y)
 //   else:    m = y_i / invd_i - sum_n w_in y_n      (A_hat y, double only).
 // The neighbour sum runs over dz, dy, dx in order.
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
   for (int v = 0; v < Epi::NV; ++v) part[v] = 0.0;
   const int64_t plane = int64_t(nx) * ny;
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
-  const acc kInf = acc(__builtin_inf());
+  const acc kOut = acc(1);  // rho of a cell outside the grid (its y is 0)
   auto ldy = [&](bool ok, int64_t j) {
     if constexpr (In::narrow) {  // as in k_stencil7: no branch around narrow loads
       const acc v = acc(in.ld(ok ? j : 0));
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
       return ok ? acc(in.ld(j)) : acc(0);
     }
   };
-  auto ldr = [&](bool ok, int64_t j) { return ok ? rho[j] : kInf; };
+  auto ldr = [&](bool ok, int64_t j) { return ok ? rho[j] : kOut; };
   const bool hy_on = ty == 0 || ty == TY - 1;  // a halo row point: row y0 - 1 or y0 + TY
   const int hy_row = ty == 0 ? 0 : TY + 1;
   const bool hx_on = ty == 1 && tx < 2 * (TY + 2);  // a halo side point (corners included)
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
     if (own) pre = epi.load(i0 + plane * z0);
     for (int z = z0; z < z1; ++z) {
       // the next plane's inputs and the next point's epilogue inputs, loaded a plane ahead
-      Vals after{acc(0), kInf, acc(0), kInf, acc(0), kInf};
+      Vals after{acc(0), kOut, acc(0), kOut, acc(0), kOut};
       typename Epi::Pre pre_next{};
       if (z + 1 < z1) {
         after = fetch(z + 2);
@@ -284,10 +285,14 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
               if (dz == 1 && dy == 1 && dx == 1) continue;
-              if constexpr (sizeof(acc) == 4)
-                off += __builtin_amdgcn_rcpf(ri + rv[dz][dy][dx]) * yv[dz][dy][dx];
-              else
-                off += yv[dz][dy][dx] / (ri + rv[dz][dy][dx]);
+              const acc d = ri + rv[dz][dy][dx];
+              if constexpr (sizeof(acc) == 4) {
+                off += __builtin_amdgcn_rcpf(d) * yv[dz][dy][dx];
+              } else {
+                double w = __builtin_amdgcn_rcp(d);
+                w = fma(fma(-d, w, 1.0), w, w);
+                off += w * yv[dz][dy][dx];
+              }
             }
           }
         }
