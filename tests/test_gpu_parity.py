@@ -399,6 +399,35 @@ def test_ragged_and_degenerate_grids(pc, dims):
     assert rel_inf(x.cpu().numpy(), ref.x_hat) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 1, 9), (65, 1, 1), (3, 5, 2), (64, 4, 17), (66, 6, 33)])
+def test_ragged_and_degenerate_grids_27(pc, dims, prec):
+    """The 27-point kernel on grids with one point, one line, one plane and ragged tiles: the
+    operator product, an apply and a solve against the oracle.  Bounds: [1e-4, 2] contains the
+    spectrum of D^-1/2 A D^-1/2 for any coefficients."""
+    kappa = W.harmonic27_kappa(*dims, seed=3)
+    rp, ci, v = W.harmonic27_csr(kappa)
+    n = len(rp) - 1
+    op = pc.Operator.stencil27h(torch.from_numpy(kappa).to(DEV))
+    lo, hi = 1e-4, 2.0
+    xin = W.uniform(21, n, -1.0, 1.0)
+    ref = oracle.nc_apply_unscaled(rp, ci, v, xin, lo, hi, 5, 1.001)
+    with pc.pcheb_setup(op, 5, lo, hi, 1.001, prec) as h:
+        y = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_matvec(h, _t(xin), y)
+        z = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, _t(xin), z)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        st = pc.pcg_solve(h, _t(xin), x, tol=1e-9, flexible=prec != "f64")
+    a = oracle.csr(rp, ci, v)
+    assert rel_inf(y.cpu().numpy(), a @ xin) <= 1e-13
+    assert rel_inf(z.cpu().numpy(), ref) <= APPLY_TOL[prec]
+    assert st["status"] == "OK" and st["relres_true"] <= 1.02e-9
+    # The exit residual the solver reports, recomputed on the host from the returned iterate.
+    res_hat = np.linalg.norm(xin - a @ x.cpu().numpy()) / np.linalg.norm(xin)
+    assert abs(res_hat - st["relres_true_hat"]) <= 1e-3 * st["relres_true_hat"] + 1e-15
+
+
 def test_graph_and_direct_launches_agree_bitwise(pc):
     c = case("h27")
     _, b = manufactured_rhs("h27")
