@@ -259,9 +259,10 @@ def main():
     avg_s = flag["step_avg_us"] * 1e-6 * S
     achieved = alg_bytes / avg_s / 1e9
     traffic = measured_traffic(args.prec, S)
+    fused_name = "k_stencil7_fused" if args.prec == "f64" else "k_stencil7_fused_buf"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": (f"k_stencil7_fused_buf<S={S},{args.prec}> ({S} middle steps per launch)" if S > 1
+                "kernel": (f"{fused_name}<S={S},{args.prec}> ({S} middle steps per launch)" if S > 1
                            else f"k_stencil7<SCALED,EpiChebStep<{args.prec}>> (middle step)"),
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_s * 1e6, 2),
                 "launches_timed": flag["step_launches"] // S,

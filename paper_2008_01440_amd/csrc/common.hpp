@@ -31,6 +31,18 @@ __device__ __forceinline__ uint16_t float_to_bf16(float f) {
   return uint16_t(u >> 16);
 }
 
+// Float64 vector outputs are stored non-temporally: a solve writes whole
+// vectors that are read again only after other vectors have streamed through
+// the L2, and the streaming store keeps the L2 for the halo and partner lines
+// a kernel is still reading (27-point float64 step 106 -> 100 us on 192^3).
+// Float32 and bfloat16 outputs keep ordinary stores, which measured faster
+// for them; the fused 7-point pass picks its own policy.
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void out_store(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void out_store2(double* p, double a, double b) {
+  __builtin_nontemporal_store(dbl2v{a, b}, reinterpret_cast<dbl2v*>(p));
+}
+
 template <class T>
 struct Store;
 
@@ -40,10 +52,8 @@ template <>
 struct Store<double> {
   using acc = double;
   static __device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; }
-  static __device__ __forceinline__ void st(double* p, int64_t i, double v) { p[i] = v; }
-  static __device__ __forceinline__ void st2(double* p, int64_t i, double a, double b) {
-    *reinterpret_cast<double2*>(p + i) = make_double2(a, b);
-  }
+  static __device__ __forceinline__ void st(double* p, int64_t i, double v) { out_store(p + i, v); }
+  static __device__ __forceinline__ void st2(double* p, int64_t i, double a, double b) { out_store2(p + i, a, b); }
 };
 
 template <>

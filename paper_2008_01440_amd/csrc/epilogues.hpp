@@ -114,7 +114,7 @@ struct EpiChebLast {
     acc v = a * y + c * (p.s - by);
     if (!FIRST) v -= b * p.yprev;
     const double zi = double(v);
-    z[i] = zi;
+    out_store(z + i, zi);
     if (DOTS) {
       part[0] += p.r * zi;
       if (flexible) part[1] += zi * p.q;
@@ -160,8 +160,8 @@ struct EpiDirection {
   using Pre = NoPre;
   __device__ __forceinline__ Pre load(int64_t) const { return {}; }
   __device__ __forceinline__ void operator()(int64_t i, double p, double ap, const Pre&, double (&part)[NV]) const {
-    if (p_new) p_new[i] = p;
-    q[i] = ap;
+    if (p_new) out_store(p_new + i, p);
+    out_store(q + i, ap);
     part[0] += p * ap;
   }
   __device__ void fin(double (&t)[NV]) const {

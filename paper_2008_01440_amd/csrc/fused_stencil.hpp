@@ -176,7 +176,12 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused(const T* __restrict__ ya,
             const acc yprev = (l == 2) ? ybc[m] : L[lp][2][m];
             v = a * yc + c * (sr[l - 2][m] - (yc - nb * sixth));  // same order as EpiChebStep
             v -= b * yprev;
-            if (l >= S && out_plane && inner[m]) Store<T>::st(out_z, col[m], v);
+            if (l >= S && out_plane && inner[m]) {
+              if constexpr (sizeof(T) == 8)
+                out_z[col[m]] = v;  // a cached store: the streaming one measured 5% slower here
+              else
+                Store<T>::st(out_z, col[m], v);
+            }
           }
           if (l <= S) {
             L[li][2][m] = L[li][1][m];
@@ -200,13 +205,23 @@ constexpr int kOutOfRange = 0x7FFFFFF0;
 template <class T>
 struct BufIo;
 
+// Cache policy of the float32 output stores: non-temporal (bit 1 of the
+// buffer instruction's cache-policy operand on this family).  A pass writes two
+// whole vectors that the next pass reads only after every other plane has
+// streamed through the L2, so keeping them there only evicts the halo lines
+// that neighbouring tiles are about to read (measured: the pass runs 3%
+// faster).  Non-temporal loads of y_{j-2}, which has no reuse either, were
+// slower, and so were non-temporal bfloat16 stores (a wavefront writes 128
+// bytes, part of two lines, and streamed partial lines cost 23%).
+constexpr int kStreamStore = 2;
+
 template <>
 struct BufIo<float> {
   static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, int off) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
   }
   static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, int off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStreamStore);
   }
 };
 

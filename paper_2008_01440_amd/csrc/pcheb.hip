@@ -543,9 +543,9 @@ __global__ void k_update(double* x, int64_t ldx, double* r, const double* p, con
   PAIR_STRIDE(i, n) {
     if (i + 1 < n) {
       const double2 xv = ld2(x, i), pv = ld2(p, i), rv = ld2(r, i), qv = ld2(q, i), w = invd2(invd, i);
-      *reinterpret_cast<double2*>(x + i) = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+      out_store2(x + i, xv.x + alpha * pv.x, xv.y + alpha * pv.y);
       const double r0 = rv.x - alpha * qv.x, r1 = rv.y - alpha * qv.y;
-      *reinterpret_cast<double2*>(r + i) = make_double2(r0, r1);
+      out_store2(r + i, r0, r1);
       part[0] += r0 * r0 * w.x + r1 * r1 * w.y;
       if (MODE == 0) {
         const double s0 = r0 * w.x, s1 = r1 * w.y;
