@@ -252,7 +252,7 @@ def main():
     # and s and writes y_j (the 7-point operator has no stored matrix): 4 e n bytes.
     # A fused pass of S steps reads the same three vectors and writes two: 5 e n bytes.
     e = {"f64": 8, "f32": 4, "bf16": 2}[args.prec]
-    S = args.fuse if args.fuse > 1 else 1
+    S = min(args.fuse, 3 if args.prec == "f64" else 4) if args.fuse > 1 else 1  # the library's clamp
     if S > 1 and (args.k - 2) % S != 0:
         log(f"note: {args.k - 2} middle steps are not a multiple of {S}; the timed launches mix pass kinds")
     alg_bytes = (5 if S > 1 else 4) * e * n

@@ -8,7 +8,9 @@
 //         = a_j y_{j-1} - b_j y_{j-2} + c_j (s - B y_{j-1}),
 // with a_j = 2 sigma rho_j, b_j = rho_j rho_{j-1} (and y_{-1} = 0, so step 1
 // drops that term), c_j = 2 rho_j / delta.  Step 1 then equals
-// (2 rho_1/delta)(2 s - B s/theta'), the first line of Alg. 2.
+// (2 rho_1/delta)(2 s - B s/theta'), the first line of Alg. 2.  y_0 itself is
+// never stored: steps 1 and 2 read s with 1/theta' folded into their
+// coefficients.
 #pragma once
 
 #include "common.hpp"

@@ -15,14 +15,29 @@ struct Coef {
   acc a, b, c;
 };
 
+// Coefficients of step j: y_j = a y_{j-1} - b y_{j-2} + c (s - B y_{j-1}).
+// y_0 = s / theta' is never stored, and 1/theta' is folded in where it would be
+// read: step 1 takes s as its input vector, so a_1 y_0 + c_1 (s - B y_0) becomes
+// (a_1/theta' + c_1 - c_1/theta') s + (c_1/theta') (s - B s); step 2 takes s for
+// y_{j-2}, so its b is b_2 / theta'.
 template <class T>
 static Coef<T> step_coef(const Handle& h, int j) {
   using acc = typename Store<T>::acc;
-  Coef<T> c;
-  c.a = acc(2.0 * h.sigma * h.rho[j]);
-  c.b = acc(j >= 1 ? h.rho[j] * h.rho[j - 1] : 0.0);
-  c.c = acc(2.0 * h.rho[j] / h.delta);
-  return c;
+  const double inv_theta = 1.0 / h.theta;
+  double a = 2.0 * h.sigma * h.rho[j];
+  double b = j >= 1 ? h.rho[j] * h.rho[j - 1] : 0.0;
+  double c = 2.0 * h.rho[j] / h.delta;
+  if (j == 1) {
+    a = a * inv_theta + c - c * inv_theta;
+    c *= inv_theta;
+  } else if (j == 2) {
+    b *= inv_theta;
+  }
+  Coef<T> cf;
+  cf.a = acc(a);
+  cf.b = acc(b);
+  cf.c = acc(c);
+  return cf;
 }
 
 // ---- fused passes (7-point stencil): S middle steps per launch

@@ -405,53 +405,41 @@ __global__ void k_zero_slots(double* p, int64_t ldw, int64_t n, int slot0) {
   GRID_STRIDE(i, n) p[i] = 0.0;
 }
 
-// Preconditioner input: s = D^-1 r and y_0 = s / theta' in the storage precision.
+// Preconditioner input: s = D^-1 r in the storage precision.
 template <class T>
-__global__ void k_prep(const double* r, int64_t ldr, T* s, T* y0, int64_t ldw, InvDiag invd, double inv_theta,
-                       int64_t n, const DevState* guard, int slot0) {
+__global__ void k_prep(const double* r, int64_t ldr, T* s, int64_t ldw, InvDiag invd, int64_t n,
+                       const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   r += slot * ldr;
   s += slot * ldw;
-  y0 += slot * ldw;
   using acc = typename Store<T>::acc;
   PAIR_STRIDE(i, n) {
     if (i + 1 < n) {
       const double2 rv = ld2(r, i), w = invd2(invd, i);
-      const double s0 = rv.x * w.x, s1 = rv.y * w.y;
-      Store<T>::st2(s, i, acc(s0), acc(s1));
-      Store<T>::st2(y0, i, acc(s0 * inv_theta), acc(s1 * inv_theta));
+      Store<T>::st2(s, i, acc(rv.x * w.x), acc(rv.y * w.y));
     } else {
-      const double si = r[i] * invd(i);
-      Store<T>::st(s, i, acc(si));
-      Store<T>::st(y0, i, acc(si * inv_theta));
+      Store<T>::st(s, i, acc(r[i] * invd(i)));
     }
   }
 }
 
-// Node blocks: s = B^-1 r and y_0 = s / theta' in the storage precision.
+// Node blocks: s = B^-1 r in the storage precision.
 template <class T>
-__global__ void k_node_prep(const double* r, int64_t ldr, T* s, T* y0, int64_t ldw, const double* binv,
-                            double inv_theta, int64_t nodes, const DevState* guard, int slot0) {
+__global__ void k_node_prep(const double* r, int64_t ldr, T* s, int64_t ldw, const double* binv, int64_t nodes,
+                            const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   r += slot * ldr;
   s += slot * ldw;
-  y0 += slot * ldw;
   using acc = typename Store<T>::acc;
   GRID_STRIDE(I, nodes) {
     const double* bi = binv + 6 * I;
     const int64_t i = 3 * I;
     const double r0 = r[i], r1 = r[i + 1], r2 = r[i + 2];
-    const double s0 = bi[0] * r0 + bi[1] * r1 + bi[2] * r2;
-    const double s1 = bi[1] * r0 + bi[3] * r1 + bi[4] * r2;
-    const double s2 = bi[2] * r0 + bi[4] * r1 + bi[5] * r2;
-    Store<T>::st(s, i, acc(s0));
-    Store<T>::st(s, i + 1, acc(s1));
-    Store<T>::st(s, i + 2, acc(s2));
-    Store<T>::st(y0, i, acc(s0 * inv_theta));
-    Store<T>::st(y0, i + 1, acc(s1 * inv_theta));
-    Store<T>::st(y0, i + 2, acc(s2 * inv_theta));
+    Store<T>::st(s, i, acc(bi[0] * r0 + bi[1] * r1 + bi[2] * r2));
+    Store<T>::st(s, i + 1, acc(bi[1] * r0 + bi[3] * r1 + bi[4] * r2));
+    Store<T>::st(s, i + 2, acc(bi[2] * r0 + bi[4] * r1 + bi[5] * r2));
   }
 }
 
@@ -515,13 +503,13 @@ __global__ void k_jacobi(const double* r, int64_t ldr, double* z, int64_t ldz, c
 
 // Iteration update x += alpha p, r -= alpha q with ||r||^2 (D^-1 weighted), and
 // the next preconditioner input fused in:
-//   MODE 0 (k >= 1): s = D^-1 r, y_0 = s / theta';
+//   MODE 0 (k >= 1): s = D^-1 r;
 //   MODE 1 (k = 0):  z = D^-1 r / theta' with (r, z), (z, q);
 //   MODE 2:          nothing else (the residual is refreshed before the next step).
 // The stop test runs in the finalize kernel (FinUpdate).
 template <class T, int MODE>
 __global__ void k_update(double* x, int64_t ldx, double* r, const double* p, const double* q, int64_t ldw,
-                         InvDiag invd, T* s, T* y0, double* z, double inv_theta, int64_t n, const DevState* st,
+                         InvDiag invd, T* s, double* z, double inv_theta, int64_t n, const DevState* st,
                          ReduceBuf rb, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   st += slot;
@@ -531,10 +519,7 @@ __global__ void k_update(double* x, int64_t ldx, double* r, const double* p, con
   r += o;
   p += o;
   q += o;
-  if (MODE == 0) {
-    s += o;
-    y0 += o;
-  }
+  if (MODE == 0) s += o;
   if (MODE == 1) z += o;
   using acc = typename Store<T>::acc;
   const double alpha = st->alpha;
@@ -548,9 +533,7 @@ __global__ void k_update(double* x, int64_t ldx, double* r, const double* p, con
       out_store2(r + i, r0, r1);
       part[0] += r0 * r0 * w.x + r1 * r1 * w.y;
       if (MODE == 0) {
-        const double s0 = r0 * w.x, s1 = r1 * w.y;
-        Store<T>::st2(s, i, acc(s0), acc(s1));
-        Store<T>::st2(y0, i, acc(s0 * inv_theta), acc(s1 * inv_theta));
+        Store<T>::st2(s, i, acc(r0 * w.x), acc(r1 * w.y));
       } else if (MODE == 1) {
         const double z0 = r0 * w.x * inv_theta, z1 = r1 * w.y * inv_theta;
         *reinterpret_cast<double2*>(z + i) = make_double2(z0, z1);
@@ -565,9 +548,7 @@ __global__ void k_update(double* x, int64_t ldx, double* r, const double* p, con
       const double w = invd(i);
       part[0] += ri * ri * w;
       if (MODE == 0) {
-        const double si = ri * w;
-        Store<T>::st(s, i, acc(si));
-        Store<T>::st(y0, i, acc(si * inv_theta));
+        Store<T>::st(s, i, acc(ri * w));
       } else if (MODE == 1) {
         const double zi = ri * w * inv_theta;
         z[i] = zi;
@@ -597,8 +578,10 @@ struct StepTimer {
 };
 
 
-// Steps 1..k of Alg. 2 on the prepared input (s, y_0 = Y[0]) of the slots; the
-// last step writes z in float64.  Every vector has the workspace stride ldw
+// Steps 1..k of Alg. 2 on the prepared input s of the slots; the last step
+// writes z in float64.  y_0 = s / theta' is not stored: step 1 reads s as its
+// input vector and step 2 reads s as y_{j-2}, with 1/theta' folded into their
+// coefficients (step_coef).  Every vector has the workspace stride ldw
 // (a single slot 0 may pass the caller's r and z: its offset is zero).
 // dots: reduce (r, z), (z, q) and form beta (inside a solve).  Middle steps
 // run S at a time when fusion is on.
@@ -611,16 +594,18 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
   T* Y[4] = {reinterpret_cast<T*>(h.Y[0]), reinterpret_cast<T*>(h.Y[1]), reinterpret_cast<T*>(h.Y[2]),
              reinterpret_cast<T*>(h.Y[3])};
   const T* sv = reinterpret_cast<const T*>(h.s);
-  int cur = 0, prev = -1;  // buffers holding y_{j-1} and y_{j-2}
+  constexpr int kY0 = -2;     // y_0, read through s
+  int cur = kY0, prev = -1;  // buffers holding y_{j-1} and y_{j-2} (-1: none)
   auto free_buf = [&](int also_avoid) {
     for (int i = 0; i < h.nY; ++i)
       if (i != cur && i != prev && i != also_avoid) return i;
     return -1;
   };
+  auto vec = [&](int b) -> const T* { return b == kY0 ? sv : b >= 0 ? Y[b] : nullptr; };
   for (int j = 1; j <= k;) {
     if (timer && k >= 3 && j == 2) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
-    const T* yin = Y[cur];
-    const T* yprev = prev >= 0 ? Y[prev] : nullptr;
+    const T* yin = vec(cur);
+    const T* yprev = vec(prev);
     const InVec<T> in{yin, ldw};
     if (j == k) {
       const Coef<T> c = step_coef<T>(h, j);
@@ -669,18 +654,16 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
   }
 }
 
-// Preconditioner input s = D^-1 r (or B^-1 r with node blocks) and y_0 = s / theta'.
+// Preconditioner input s = D^-1 r (or B^-1 r with node blocks).
 template <class T>
 static void enqueue_prep(Handle& h, Slots sl, const double* r, int64_t ldr, const DevState* guard, hipStream_t s) {
   const int64_t n = h.n;
   if (h.bs == 3)
-    k_node_prep<T><<<dim3(flat_grid(n / 3), sl.count), kBlock, 0, s>>>(
-        r, ldr, reinterpret_cast<T*>(h.s), reinterpret_cast<T*>(h.Y[0]), h.ldw, h.binv, 1.0 / h.theta, n / 3,
-        guard, sl.first);
+    k_node_prep<T><<<dim3(flat_grid(n / 3), sl.count), kBlock, 0, s>>>(r, ldr, reinterpret_cast<T*>(h.s), h.ldw,
+                                                                        h.binv, n / 3, guard, sl.first);
   else
-    k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(r, ldr, reinterpret_cast<T*>(h.s),
-                                                              reinterpret_cast<T*>(h.Y[0]), h.ldw, invdiag(h),
-                                                              1.0 / h.theta, n, guard, sl.first);
+    k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(r, ldr, reinterpret_cast<T*>(h.s), h.ldw, invdiag(h),
+                                                              n, guard, sl.first);
 }
 
 // Stand-alone application r -> z (caller vectors) on slot 0 of the workspace.
@@ -1137,7 +1120,7 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
     launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{nullptr, h.q, st, st, h.ldw}, sl.first, sl.count, s);
   }
   if (refresh) {
-    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
+    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
     k_finalize<3, FinUpdate<2>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
     launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, h.r, invdiag(h), st, st, 2, ldb, h.ldw}, sl.first, sl.count,
@@ -1146,18 +1129,17 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
     return;
   }
   if (h.bs == 3) {  // node blocks: the preconditioner input needs whole nodes, so it is a pass of its own
-    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, nullptr, 0.0,
+    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
     k_finalize<3, FinUpdate<2>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
     enqueue_precond<T>(h, sl, 0, flexible, timer, s);
   } else if (h.prm.k == 0) {
-    k_update<double, 1><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, h.z,
+    k_update<double, 1><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, h.z,
                                                 1.0 / h.theta, n, st, h.rb(), sl.first);
     k_finalize<3, FinUpdate<1>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st, sl.first);
   } else {
     k_update<T, 0><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), reinterpret_cast<T*>(h.s),
-                                           reinterpret_cast<T*>(h.Y[0]), nullptr, 1.0 / h.theta, n, st, h.rb(),
-                                           sl.first);
+                                           nullptr, 1.0 / h.theta, n, st, h.rb(), sl.first);
     k_finalize<3, FinUpdate<0>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st, sl.first);
     if (h.prm.form == PCHEB_FORM_NEWTON)
       enqueue_newton<T>(h, sl, h.z, h.ldw, h.r, h.ldw, h.q, true, 0, flexible, st, s);
