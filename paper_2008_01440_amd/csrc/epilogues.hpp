@@ -13,6 +13,8 @@
 // coefficients.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace pcheb {
@@ -65,8 +67,14 @@ struct EpiChebStep {
   __device__ void fin(double (&)[NV]) const {}
 };
 
-// Last step: z = y_k in float64 and, inside a solve, the partial sums of
-// (r, z) and (z, q).  The last block then forms, on the device,
+// Type of z written by the last step: inside a solve (DOTS) a float32 or
+// bfloat16 recurrence stores z in float32, which holds its float32 arithmetic
+// exactly and halves the traffic of z; otherwise float64.
+template <class T, bool DOTS>
+using ChebZ = std::conditional_t<DOTS && !std::is_same<T, double>::value, float, double>;
+
+// Last step: z = y_k (float64, or float32 as ChebZ says) and, inside a solve,
+// the partial sums of (r, z) and (z, q).  The last block then forms, on the device,
 //   gamma_new = (r, z);
 //   beta = gamma_new / gamma                     (Fletcher-Reeves), or
 //   beta = (z, r - r_old) / gamma = -(z, q)/(p, q) (Polak-Ribiere; r - r_old = -alpha q
@@ -78,9 +86,10 @@ struct EpiChebLast {
   using acc = typename Store<T>::acc;
   static constexpr int NV = 2;
   static constexpr bool reduce = DOTS;
+  using Tz = ChebZ<T, DOTS>;
   const T* yprev;
   const T* s;
-  double* z;
+  Tz* z;
   const double* r;  // float64 residual (for the dot products)
   const double* q;  // A p of this iteration (flexible beta only)
   acc a, b, c;
@@ -116,7 +125,10 @@ struct EpiChebLast {
     acc v = a * y + c * (p.s - by);
     if (!FIRST) v -= b * p.yprev;
     const double zi = double(v);
-    out_store(z + i, zi);
+    if constexpr (std::is_same<Tz, double>::value)
+      out_store(z + i, zi);
+    else
+      z[i] = float(v);
     if (DOTS) {
       part[0] += p.r * zi;
       if (flexible) part[1] += zi * p.q;

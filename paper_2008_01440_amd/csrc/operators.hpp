@@ -424,10 +424,11 @@ struct InVec {
 
 // p = z + beta * p_old, formed where it is read (beta from the solver state).
 // The 7-point kernel calls ld once per point of a tile plane and its halo.
+template <class Tz>
 struct InDirection {
   using acc = double;
   static constexpr bool narrow = false;
-  const double* z;
+  const Tz* z;  // float when the preconditioner's output has float32 precision (stored exactly)
   const double* p_old;
   const DevState* st;
   double beta;
@@ -438,7 +439,7 @@ struct InDirection {
     st += slot;
   }
   __device__ __forceinline__ void prepare() { beta = st->beta; }
-  __device__ __forceinline__ double ld(int64_t i) const { return z[i] + beta * p_old[i]; }
+  __device__ __forceinline__ double ld(int64_t i) const { return double(z[i]) + beta * p_old[i]; }
 };
 
 // v scaled by D^-1/2 (for the symmetric scaled operator of the Lanczos estimator).

@@ -379,7 +379,8 @@ __global__ void k_start_zero(const double* b, int64_t ldb, double* x, int64_t ld
 // its own for the operators whose kernels read an input value more than once
 // (CSR and SELL gathers, the 27-point stencil); the 7-point kernel forms p as
 // it stages each plane.
-__global__ void k_direction(const double* z, const double* p_old, double* p, int64_t ldw, int64_t n,
+template <class Tz>
+__global__ void k_direction(const Tz* z, const double* p_old, double* p, int64_t ldw, int64_t n,
                             const DevState* st, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   st += slot;
@@ -391,10 +392,10 @@ __global__ void k_direction(const double* z, const double* p_old, double* p, int
   const double beta = st->beta;
   PAIR_STRIDE(i, n) {
     if (i + 1 < n) {
-      const double2 zv = ld2(z, i), pv = ld2(p_old, i);
-      *reinterpret_cast<double2*>(p + i) = make_double2(zv.x + beta * pv.x, zv.y + beta * pv.y);
+      const double2 pv = ld2(p_old, i);
+      *reinterpret_cast<double2*>(p + i) = make_double2(double(z[i]) + beta * pv.x, double(z[i + 1]) + beta * pv.y);
     } else {
-      p[i] = z[i] + beta * p_old[i];
+      p[i] = double(z[i]) + beta * p_old[i];
     }
   }
 }
@@ -602,6 +603,7 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
     return -1;
   };
   auto vec = [&](int b) -> const T* { return b == kY0 ? sv : b >= 0 ? Y[b] : nullptr; };
+  ChebZ<T, true>* zs = reinterpret_cast<ChebZ<T, true>*>(z);  // z inside a solve (dots)
   for (int j = 1; j <= k;) {
     if (timer && k >= 3 && j == 2) PCHEB_HIP_CHECK(hipEventRecord(timer->next(h), s));
     const T* yin = vec(cur);
@@ -611,7 +613,7 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
       const Coef<T> c = step_coef<T>(h, j);
       if (j == 1) {
         if (dots)
-          launch_bop<T>(h, in, EpiChebLast<T, true, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init,
+          launch_bop<T>(h, in, EpiChebLast<T, true, true>{yprev, sv, zs, r, q, c.a, c.b, c.c, h.st, guard, init,
                                                           flexible, ldw},
                         sl.first, sl.count, s);
         else
@@ -620,7 +622,7 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
                         sl.first, sl.count, s);
       } else {
         if (dots)
-          launch_bop<T>(h, in, EpiChebLast<T, false, true>{yprev, sv, z, r, q, c.a, c.b, c.c, h.st, guard, init,
+          launch_bop<T>(h, in, EpiChebLast<T, false, true>{yprev, sv, zs, r, q, c.a, c.b, c.c, h.st, guard, init,
                                                            flexible, ldw},
                         sl.first, sl.count, s);
         else
@@ -1101,6 +1103,28 @@ static void enqueue_start(Handle& h, Slots sl, const double* b, int64_t ldb, dou
   enqueue_precond<T>(h, sl, 1, flexible, timer, s);
 }
 
+// Inside a solve, a float32 or bfloat16 recurrence leaves z in float32 (its
+// last step computes in float32, so the float32 store is exact); the float64
+// recurrence, degree 0 and the Newton form leave it in float64.
+template <class T>
+static bool z_is_float(const Handle& h) {
+  return !std::is_same<T, double>::value && h.prm.k >= 1 && h.prm.form == PCHEB_FORM_CHEBYSHEV;
+}
+
+// p = z + beta p_old and q = A p with (p, q) (alpha formed on the device).
+template <class Tz>
+static void enqueue_direction(Handle& h, Slots sl, const Tz* z, const double* p_old, double* p_new, hipStream_t s) {
+  DevState* st = h.st;
+  if (h.op.kind == PCHEB_OP_STENCIL7) {
+    // the 7-point kernel reads each input point once: form p there and store it beside q
+    launch_ahat(h, InDirection<Tz>{z, p_old, st, 0.0, h.ldw}, EpiDirection{p_new, h.q, st, st, h.ldw}, sl.first,
+                sl.count, s);
+  } else {
+    k_direction<<<dim3(pair_grid(h.n), sl.count), kBlock, 0, s>>>(z, p_old, p_new, h.ldw, h.n, st, sl.first);
+    launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{nullptr, h.q, st, st, h.ldw}, sl.first, sl.count, s);
+  }
+}
+
 // One PCG iteration on the slots: p = z + beta p_old, q = A p, the update with the
 // fused preconditioner input, and the k recurrence steps (beta formed on the device).
 template <class T>
@@ -1111,14 +1135,10 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
   double* p_new = h.p[cur ^ 1];
   const uint32_t g = pair_grid(n);
   const dim3 grid(g, sl.count);
-  if (h.op.kind == PCHEB_OP_STENCIL7) {
-    // the 7-point kernel reads each input point once: form p there and store it beside q
-    launch_ahat(h, InDirection{h.z, h.p[cur], st, 0.0, h.ldw}, EpiDirection{p_new, h.q, st, st, h.ldw}, sl.first,
-                sl.count, s);
-  } else {
-    k_direction<<<grid, kBlock, 0, s>>>(h.z, h.p[cur], p_new, h.ldw, n, st, sl.first);
-    launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{nullptr, h.q, st, st, h.ldw}, sl.first, sl.count, s);
-  }
+  if (z_is_float<T>(h))
+    enqueue_direction(h, sl, reinterpret_cast<const float*>(h.z), h.p[cur], p_new, s);
+  else
+    enqueue_direction(h, sl, static_cast<const double*>(h.z), h.p[cur], p_new, s);
   if (refresh) {
     k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0,
                                            n, st, h.rb(), sl.first);
