@@ -50,6 +50,7 @@ static Coef<T> step_coef(const Handle& h, int j) {
 #define PCHEB_FUSED_NT 1024
 #endif
 
+
 template <class T, int S, int TY, int NT>
 static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T* oa, T* ob, int j,
                          const DevState* guard, hipStream_t s) {
@@ -63,9 +64,13 @@ static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T*
   const pcheb_operator& op = h.op;
   const uint32_t tiles_x = uint32_t((op.nx + 63) / 64), tiles_y = uint32_t((op.ny + TY - 1) / TY);
   const uint32_t xy = tiles_x * tiles_y;
-  // about as many tiles as the chip holds blocks at once (256 CUs, 1024 threads
-  // each in flight), each z range at least 4 S planes deep
-  const uint32_t target = 262144u / NT;
+  // about as many tiles as the chip holds blocks at once (256 CUs; per CU at
+  // most 2048 threads and 160 KiB of LDS), each z range at least 4 S planes deep
+  constexpr int RX = 64 + 2 * S, NP = RX * (TY + 2 * S);
+  constexpr int kLds = sizeof(T) < 8 ? (NP + 2 * (RX + 1)) * ((3 * S) % 2 == 0 ? 3 * S + 1 : 3 * S) * 4
+                                     : S * 2 * NP * int(sizeof(typename Store<T>::acc));
+  constexpr int kPerCu = std::max(1, std::min(2048 / NT, 163840 / kLds));
+  const uint32_t target = 256u * kPerCu;
   const int max_chunks = std::max(1, op.nz / (4 * S));
   const int chunks = std::max(1, std::min<int>(max_chunks, int((target + xy - 1) / xy)));
   const int zc = (op.nz + chunks - 1) / chunks;

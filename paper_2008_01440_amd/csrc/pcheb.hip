@@ -632,13 +632,14 @@ static void enqueue_steps(Handle& h, Slots sl, double* z, const double* r, const
       }
       break;
     }
-    if (j >= 2 && S >= 2 && j + S - 1 <= k - 1) {
+    const int Sj = std::min(S, k - j);  // steps of this pass: at most S, and step k stays single
+    if (j >= 2 && Sj >= 2) {
       const int ob = free_buf(-1);
       const int oa = free_buf(ob);
-      launch_fused_any<T>(h, sl, S, yin, yprev, Y[oa], Y[ob], j, guard, s);
+      launch_fused_any<T>(h, sl, Sj, yin, yprev, Y[oa], Y[ob], j, guard, s);
       prev = ob;
       cur = oa;
-      j += S;
+      j += Sj;
     } else {
       const int o = free_buf(-1);
       const Coef<T> c = step_coef<T>(h, j);

@@ -472,7 +472,7 @@ FUSED_DIMS = [(67, 13, 19), (130, 33, 40), (64, 8, 16)]
 
 @pytest.mark.parametrize("prec,S", [("f64", 2), ("f64", 3), ("f32", 2), ("f32", 3), ("f32", 4),
                                     ("bf16", 2), ("bf16", 4)])
-@pytest.mark.parametrize("k", [3, 6, 11, 31])
+@pytest.mark.parametrize("k", [3, 6, 8, 11, 31])  # 8: a shorter last pass for S = 4
 @pytest.mark.parametrize("dims", FUSED_DIMS)
 def test_fused_apply_matches_oracle_and_unfused(pc, dims, k, prec, S):
     rp, ci, v = W.stencil7_csr(*dims)
