@@ -454,17 +454,21 @@ def test_kernel_timing_counts(pc):
     assert st["step_ms"] > 0.0
 
 
-def test_residual_refresh_keeps_convergence(pc):
-    c = case("csr7")
-    _, b = manufactured_rhs("csr7")
+@pytest.mark.parametrize("name,k,tol", [("csr7", 0, 1e-8), ("st7", 2, 1e-12)])
+def test_residual_refresh_keeps_convergence(pc, name, k, tol):
+    """Periodic replacement of the recursive residual (every 50 iterations), with degree 0 on CSR and
+    with a degree-2 preconditioner on the matrix-free 7-point operator (the oracle takes 58
+    iterations for that case at this tolerance)."""
+    c = case(name)
+    _, b = manufactured_rhs(name)
     res = []
-    with pc.pcheb_setup(c.operator(torch, DEV), 0, c.lo, c.hi, 1.0) as h:
+    with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.0) as h:
         for refresh in (False, True):
             x = torch.zeros(c.n, dtype=torch.float64, device=DEV)
-            st = pc.pcg_solve(h, _t(b), x, refresh=refresh)
+            st = pc.pcg_solve(h, _t(b), x, tol=tol, refresh=refresh)
             res.append(st)
-    assert res[0]["iters"] > 50
-    assert abs(res[0]["iters"] - res[1]["iters"]) <= 2 and res[1]["relres_true"] <= TRUE_RES
+    assert res[0]["iters"] > 50  # so the refreshed solve replaces its residual at least once
+    assert abs(res[0]["iters"] - res[1]["iters"]) <= 2 and res[1]["relres_true"] <= 1.02 * tol
 
 
 FUSED_DIMS = [(67, 13, 19), (130, 33, 40), (64, 8, 16)]
