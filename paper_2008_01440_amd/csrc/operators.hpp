@@ -354,6 +354,14 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
     const int32_t rb_lane = rowptr[myrow < n ? myrow : n];
     const int32_t re_lane = rowptr[myrow + 1 < n ? myrow + 1 : n];
     acc mine = acc(0);
+    // the epilogue's own inputs are loaded before the row sums, so their latency overlaps them
+    const bool has_row = lane < kRows && myrow < n;
+    typename Epi::Pre pre{};
+    acc yi = acc(0);
+    if (has_row) {
+      pre = epi.load(myrow);
+      yi = in.ld(myrow);
+    }
     for (int it = 0; it < PASSES; ++it) {
       const int r = it * kGroups + grp;  // row of this group in this pass (rows past n are empty)
       const int32_t b = __shfl(rb_lane, r, kWave), e = __shfl(re_lane, r, kWave);
@@ -364,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
       const acc v = __shfl(sum, (lane % kGroups) * LANES, kWave);  // row it * kGroups + lane % kGroups
       if (lane / kGroups == it) mine = v;
     }
-    if (lane < kRows && myrow < n) epi(myrow, in.ld(myrow), mine, epi.load(myrow), part);
+    if (has_row) epi(myrow, yi, mine, pre, part);
   }
   finish_reduction(epi, part, rb, slot);
 }
@@ -395,16 +403,22 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
     if (chunk * kWave >= n) continue;
     const int64_t base = chunk_ptr[chunk];
     const int32_t len = chunk_len[chunk];
+    // the epilogue's own inputs are loaded before the row sums, so their latency overlaps them
+    const bool has_row = pos < n;
+    const int64_t row = has_row ? (perm ? int64_t(perm[pos]) : pos) : 0;
+    typename Epi::Pre pre{};
+    acc yi = acc(0);
+    if (has_row) {
+      pre = epi.load(row);
+      yi = in.ld(row);
+    }
     acc sum = acc(0);
 #pragma unroll 8
     for (int32_t j = 0; j < len; ++j) {  // unrolled: several slots' loads in flight, same summation order
       const int64_t e = base + int64_t(j) * kWave + lane;
       sum += acc(Store<Tv>::ld(val, e)) * in.ld(col[e]);
     }
-    if (pos < n) {
-      const int64_t row = perm ? int64_t(perm[pos]) : pos;
-      epi(row, in.ld(row), sum, epi.load(row), part);
-    }
+    if (has_row) epi(row, yi, sum, pre, part);
   }
   finish_reduction(epi, part, rb, slot);
 }
