@@ -428,6 +428,38 @@ def test_ragged_and_degenerate_grids_27(pc, dims, prec):
     assert abs(res_hat - st["relres_true_hat"]) <= 1e-3 * st["relres_true_hat"] + 1e-15
 
 
+@pytest.mark.parametrize("max_off", [13, 29])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_csr_wide_rows_of_mixed_length(pc, max_off, prec):
+    """CSR with more than 2^20 rows (64 rows per wavefront, 4 or 8 lanes per row): rows of 1 to
+    max_off + 1 nonzeros, so some rows end inside the first two slots of a pass and some continue in
+    the remainder loop, and a ragged last wavefront.  Operator product and an apply against the oracle
+    on the same matrix (a diagonal in [5, 6] plus random off-diagonal entries in [-1, 1])."""
+    import scipy.sparse as sp
+    n = (1 << 20) + 37
+    rng = np.random.default_rng(41 + max_off)
+    lens = rng.integers(0, max_off + 1, n)
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(0, n, int(lens.sum()))
+    a = sp.csr_matrix((rng.uniform(-1.0, 1.0, int(lens.sum())), (rows, cols)), shape=(n, n))
+    a = (a + sp.diags(rng.uniform(5.0, 6.0, n))).tocsr()
+    a.sum_duplicates()
+    a.sort_indices()
+    rp, ci, v = a.indptr.astype(np.int32), a.indices.astype(np.int32), a.data
+    xin = W.uniform(23, n, -1.0, 1.0)
+    lo, hi, k = 0.2, 1.8, 3
+    ref = oracle.nc_apply_unscaled(rp, ci, v, xin, lo, hi, k, 1.001)
+    op = pc.Operator.csr(_t(rp), _t(ci), _t(v))
+    with pc.pcheb_setup(op, k, lo, hi, 1.001, prec) as h:
+        y = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_matvec(h, _t(xin), y)
+        z = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, _t(xin), z)
+        torch.cuda.synchronize()
+    assert rel_inf(y.cpu().numpy(), a @ xin) <= 1e-13
+    assert rel_inf(z.cpu().numpy(), ref) <= APPLY_TOL[prec]
+
+
 def test_graph_and_direct_launches_agree_bitwise(pc):
     c = case("h27")
     _, b = manufactured_rhs("h27")
