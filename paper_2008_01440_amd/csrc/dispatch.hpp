@@ -15,7 +15,13 @@ namespace pcheb {
 #ifndef PCHEB_ST7_ZC
 #define PCHEB_ST7_ZC 16
 #endif
-constexpr int64_t kCsrWideRows = int64_t(1) << 20;  // CSR: 64 rows per wavefront from this row count on
+// CSR: from kCsrWideRows rows on, a wavefront walks min(L, kCsrWidePasses)
+// passes of 64 / L rows (L lanes per row); below, one pass.  Four passes keep
+// eight nonzero slots per lane in flight in the straight-line part of k_csr
+// (elasticity, L = 32: 32 passes 1270 us, 8 passes 1095 us, 4 passes 988 us,
+// 2 passes 1030 us per F32 step).
+constexpr int64_t kCsrWideRows = int64_t(1) << 20;
+constexpr int kCsrWidePasses = 4;
 constexpr int kSt7Rows = PCHEB_ST7_TY;    // grid rows per stencil tile (waves per block), 7- and 27-point
 constexpr int kSt7ZChunk = PCHEB_ST7_ZC;  // planes marched per stencil tile
 
@@ -60,15 +66,16 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       break;
     }
     case PCHEB_OP_CSR: {
-      // 64 rows per wavefront for large matrices, 64 / lanes (one pass) for small ones
+      // min(L, kCsrWidePasses) passes per wavefront for large matrices, one for small ones
       const bool wide = h.n >= kCsrWideRows;
 #define PCHEB_CSR_CASE(L)                                                                                  \
   case L: {                                                                                                \
-    const int64_t rows = int64_t(kBlock / kWave) * (wide ? kWave : kWave / L);                             \
+    constexpr int PW = L < kCsrWidePasses ? L : kCsrWidePasses;                                            \
+    const int64_t rows = int64_t(kBlock / kWave) * (wide ? PW * (kWave / L) : kWave / L);                  \
     const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);                                              \
     grid = round_grid(tiles);                                                                              \
     if (wide)                                                                                              \
-      k_csr<L, L, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \
+      k_csr<L, PW, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \
                                                                      h.n, uint32_t(tiles), h.rb(), slot0); \
     else                                                                                                   \
       k_csr<L, 1, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \

@@ -326,13 +326,13 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
 // consecutive rows and walks them in PASSES passes of 64 / LANES rows; after
 // each pass lane L picks up the sum of row L from its group, so the epilogue
 // runs once per wavefront on consecutive rows with unit-stride vector
-// accesses.  PASSES = LANES (64 rows per wavefront, every lane busy in the
-// epilogue) suits large matrices; PASSES = 1 keeps each wavefront's serial
-// chain short for small ones, where launch latency dominates.  With up to 8
-// passes, the first two nonzero slots of every pass are read in straight-line
-// code before any sum is formed, so all passes' loads are in flight together
-// (7-point F32 step 347 -> 311 us on 256^3); longer rows finish in a loop.  A
-// tile is the rows of one block.
+// accesses.  Large matrices take PASSES = min(LANES, 4) (for 4 lanes per row
+// 64 rows per wavefront, every lane busy in the epilogue); PASSES = 1 keeps
+// each wavefront's serial chain short for small ones, where launch latency
+// dominates.  With up to 8 passes, the first two nonzero slots of every pass
+// are read in straight-line code before any sum is formed, so all passes'
+// loads are in flight together (7-point F32 step 347 -> 311 us on 256^3);
+// longer rows finish in a loop.  A tile is the rows of one block.
 template <int LANES, int PASSES, class Tv, class In, class Epi>
 __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                 const Tv* __restrict__ val, In in, Epi epi, int64_t n,
