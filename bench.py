@@ -203,7 +203,7 @@ def main():
     if "c2" in configs:
         rows = []
         for k in (0, 5, 20, 50, 100):
-            for kind, prec, fuse in (("stencil7", "f64", 3), ("stencil7", "f32", 4), ("stencil7", "bf16", 4),
+            for kind, prec, fuse in (("stencil7", "f64", 4), ("stencil7", "f32", 4), ("stencil7", "bf16", 4),
                                      ("csr", "f64", 1), ("csr", "f32", 1)):
                 if k == 0 and prec != "f64":
                     continue
@@ -225,7 +225,7 @@ def main():
                     if k == 0 and prec != "f64":
                         continue
                     for fuse in (int(f) for f in args.sweep_fuse.split(",")):
-                        if fuse > 1 and (kind != "stencil7" or k < 3 or (prec == "f64" and fuse > 3)):
+                        if fuse > 1 and (kind != "stencil7" or k < 3):
                             continue
                         rows.append(run(kind, k, prec, 2, 1, time_kernels=k >= 3, fuse=fuse))
         print(json.dumps({"sweep": rows}))
@@ -245,14 +245,14 @@ def main():
     if not args.no_variants:
         log("variants:")
         variants["fp64_plain_pcg"] = run("stencil7", 0, "f64", max(2, args.steps // 4), 1)
-        variants["fp64_nc"] = run("stencil7", args.k, "f64", 2, 1, time_kernels=True, fuse=min(args.fuse, 3))
+        variants["fp64_nc"] = run("stencil7", args.k, "f64", 2, 1, time_kernels=True, fuse=args.fuse)
         variants["csr_" + args.prec + "_nc"] = run("csr", args.k, args.prec, 2, 1, time_kernels=True)
 
     # roofline of the dominant kernel.  A middle Chebyshev step reads y_{j-1}, y_{j-2}
     # and s and writes y_j (the 7-point operator has no stored matrix): 4 e n bytes.
     # A fused pass of S steps reads the same three vectors and writes two: 5 e n bytes.
     e = {"f64": 8, "f32": 4, "bf16": 2}[args.prec]
-    S = min(args.fuse, 3 if args.prec == "f64" else 4) if args.fuse > 1 else 1  # the library's clamp
+    S = min(args.fuse, 4) if args.fuse > 1 else 1  # the library's clamp
     if S > 1 and (args.k - 2) % S != 0:
         log(f"note: {args.k - 2} middle steps are not a multiple of {S}; the timed launches mix pass kinds")
     alg_bytes = (5 if S > 1 else 4) * e * n

@@ -96,8 +96,9 @@ typedef struct pcheb_operator {
  * first); lambda_max below the true largest eigenvalue makes p_k(A) A
  * indefinite for odd k.  theta_scale is the modified parameter s of Sec. 4
  * (1 gives the min-max optimal polynomial; the paper uses 1.01 and 1.001).
- * fuse_steps > 1 asks the matrix-free stencil paths to run that many
- * recurrence steps per pass over memory (ignored elsewhere; 0 or 1 = off).
+ * fuse_steps > 1 asks the matrix-free 7-point path to run that many
+ * recurrence steps per pass over memory, at most 4 (larger values act as 4;
+ * ignored for other operators; 0 or 1 = off).
  * form selects how the same polynomial is applied (Theorem 2 makes them
  * equal in exact arithmetic): PCHEB_FORM_CHEBYSHEV, the three-term
  * recurrence of Alg. 2 (any k); PCHEB_FORM_NEWTON, the recursion of Alg. 1,

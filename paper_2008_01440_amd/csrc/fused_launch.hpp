@@ -97,6 +97,8 @@ static void launch_fused_any(const Handle& h, Slots sl, int S, const T* ya, cons
   if constexpr (sizeof(T) == 8) {
     if (S == 2)
       launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+    else if (S == 4)  // float64 rings of four levels fit 128 registers and 160 KiB of LDS on 64 x 16 tiles
+      launch_fused<T, 4, 16, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
     else
       launch_fused<T, 3, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
   } else {

@@ -990,7 +990,7 @@ static void setup_preconditioner(Handle& h, hipStream_t s) {
   chebyshev_scalars(h);
   h.elem = storage_bytes(h.prm.prec);
   PCHEB_BY_PREC(h, build_scaled_values, h, s);
-  h.fuse = std::max(1, std::min(h.prm.fuse_steps, h.prm.prec == PCHEB_F64 ? 3 : 4));
+  h.fuse = std::max(1, std::min(h.prm.fuse_steps, 4));
   h.nY = (h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2) ? 4 : 3;
   h.ldw = round_up(h.n, 64);
 }

@@ -59,10 +59,10 @@ def _sampled_apply(rp_box_fn, r3, centre, dims, k, lo, hi, s=1.001):
 
 
 SAMPLES_256 = [(0, 0, 0), (255, 255, 255), (128, 128, 128), (63, 31, 31), (64, 32, 32), (127, 200, 95),
-               (255, 0, 160)]
+               (255, 0, 160), (10, 16, 64), (200, 15, 63)]  # the last two: 64 x 16 tiles, 64-plane ranges
 
 
-@pytest.mark.parametrize("prec,fuse", [("f32", 4), ("f64", 3)])
+@pytest.mark.parametrize("prec,fuse", [("f32", 4), ("f64", 4)])
 def test_apply_256_sampled(pc, prec, fuse):
     """256^3 7-point, k = 50 (the benchmark's apply: F32, four steps per pass)."""
     N, k = 256, 50

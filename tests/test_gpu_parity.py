@@ -506,7 +506,7 @@ def test_residual_refresh_keeps_convergence(pc, name, k, tol):
 FUSED_DIMS = [(67, 13, 19), (130, 33, 40), (64, 8, 16)]
 
 
-@pytest.mark.parametrize("prec,S", [("f64", 2), ("f64", 3), ("f32", 2), ("f32", 3), ("f32", 4),
+@pytest.mark.parametrize("prec,S", [("f64", 2), ("f64", 3), ("f64", 4), ("f32", 2), ("f32", 3), ("f32", 4),
                                     ("bf16", 2), ("bf16", 4)])
 @pytest.mark.parametrize("k", [3, 6, 8, 11, 31])  # 8: a shorter last pass for S = 4
 @pytest.mark.parametrize("dims", FUSED_DIMS)
@@ -528,7 +528,7 @@ def test_fused_apply_matches_oracle_and_unfused(pc, dims, k, prec, S):
     assert rel_inf(outs[1], outs[0]) <= {"f64": 1e-14, "f32": 1e-6, "bf16": 2e-2}[prec]
 
 
-@pytest.mark.parametrize("prec,S", [("f64", 3), ("f32", 4), ("bf16", 4)])
+@pytest.mark.parametrize("prec,S", [("f64", 4), ("f32", 4), ("bf16", 4)])
 def test_fused_solve_matches_oracle(pc, prec, S):
     c = case("st7_cube")
     k = 22
