@@ -580,7 +580,8 @@ struct StepTimer {
 
 
 // Steps 1..k of Alg. 2 on the prepared input s of the slots; the last step
-// writes z in float64.  y_0 = s / theta' is not stored: step 1 reads s as its
+// writes z (float64, or float32 inside a solve with a float32 or bfloat16
+// recurrence: ChebZ).  y_0 = s / theta' is not stored: step 1 reads s as its
 // input vector and step 2 reads s as y_{j-2}, with 1/theta' folded into their
 // coefficients (step_coef).  Every vector has the workspace stride ldw
 // (a single slot 0 may pass the caller's r and z: its offset is zero).
