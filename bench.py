@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=128.0)
     ap.add_argument("--serve-k", type=int, default=30)
     ap.add_argument("--serve-prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--serve-fuse", type=int, default=4, help="steps per pass of the 7-point requests")
     ap.add_argument("--configs", default="",
                     help="comma-separated subset of c1,c2,c3,c4: per-configuration measurements, one JSON line each")
     ap.add_argument("--paper-scale", default="",
@@ -632,7 +633,7 @@ def run_serve(args, rate, torch, pc, W, dev):
             lo, hi = bounds[(kind, N)]
             try:
                 rid = srv.submit(ops[(kind, N)], b, x, args.serve_k, tol=1e-8, prec=args.serve_prec,
-                                 lambda_min=lo, lambda_max=hi, fuse_steps=2 if kind == 0 else 1)
+                                 lambda_min=lo, lambda_max=hi, fuse_steps=args.serve_fuse if kind == 0 else 1)
                 outstanding[rid] = (i, b, x)
             except pc.PchebError as e:
                 if e.name != "BUDGET":
@@ -673,7 +674,7 @@ def run_serve(args, rate, torch, pc, W, dev):
             lo, hi = pc.pcheb_estimate_bounds(op, v0, 30)
             hi *= 1.01
         with pc.pcheb_setup(op, args.serve_k, lo, hi, 1.001, args.serve_prec,
-                            fuse_steps=2 if kind == 0 else 1) as h:
+                            fuse_steps=args.serve_fuse if kind == 0 else 1) as h:
             x1 = torch.empty_like(x)
             st1 = pc.pcg_solve(h, b, x1, tol=1e-8, flexible=True)
         same += int(torch.equal(x, x1) and st1["iters"] == st["iters"])
