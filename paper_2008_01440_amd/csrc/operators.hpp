@@ -28,6 +28,8 @@
 // SELL it is whatever value array the caller passes.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace pcheb {
@@ -166,7 +168,9 @@ __global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, in
 // rho = 1 / (2 kappa) with its one-point halo (corners included) in LDS, two
 // buffers and one barrier per plane.  Each thread copies its 3 x 3
 // neighbourhood of the staged plane into a register ring of three planes, so
-// a point's 26 neighbours cost 18 LDS reads per plane instead of 18 loads.
+// a point's 26 neighbours cost 18 LDS reads per plane instead of 18 loads;
+// the z loop is unrolled by three, the ring's period, so its slots are fixed
+// per phase and the ring is never shifted.
 // The face weight 2 k_i k_n / (k_i + k_n) is 1 / (rho_i + rho_n): one add and
 // the hardware reciprocal, refined in double by one Newton-Raphson step
 // r <- r + r (1 - x r).  Cells outside the grid read y = 0 and rho = 1 (any
@@ -265,54 +269,63 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
     stage(fetch(z0), 1);
     Vals nxt = fetch(z0 + 1);
     typename Epi::Pre pre{};
-    if (own) pre = epi.load(i0 + plane * z0);
-    for (int z = z0; z < z1; ++z) {
+    acc dinv = acc(0);  // D^-1 at the point
+    if (own) {
+      pre = epi.load(i0 + plane * z0);
+      dinv = invd[i0 + plane * z0];
+    }
+    // One plane; PH = (z - z0) mod 3 names the ring slots (below, at and above
+    // the point: PH, PH + 1, PH + 2 mod 3), so the ring needs no moves.
+    auto step = [&](auto phase, int z) {
+      constexpr int PH = decltype(phase)::value;
       // the next plane's inputs and the next point's epilogue inputs, loaded a plane ahead
       Vals after{acc(0), kOut, acc(0), kOut, acc(0), kOut};
       typename Epi::Pre pre_next{};
+      acc dinv_next = acc(0);
       if (z + 1 < z1) {
         after = fetch(z + 2);
-        if (own) pre_next = epi.load(i0 + plane * (z + 1));
+        if (own) {
+          pre_next = epi.load(i0 + plane * (z + 1));
+          dinv_next = invd[i0 + plane * (z + 1)];
+        }
       }
-      stage(nxt, 2);
+      stage(nxt, (PH + 2) % 3);
       if (own) {
-        const acc ri = rv[1][1][1];
+        constexpr int C = (PH + 1) % 3;
+        const acc ri = rv[C][1][1];
         acc off = acc(0);
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
+          const int q = (PH + dz) % 3;
 #pragma unroll
           for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
               if (dz == 1 && dy == 1 && dx == 1) continue;
-              const acc d = ri + rv[dz][dy][dx];
+              const acc d = ri + rv[q][dy][dx];
               if constexpr (sizeof(acc) == 4) {
-                off += __builtin_amdgcn_rcpf(d) * yv[dz][dy][dx];
+                off += __builtin_amdgcn_rcpf(d) * yv[q][dy][dx];
               } else {
                 double w = __builtin_amdgcn_rcp(d);
                 w = fma(fma(-d, w, 1.0), w, w);
-                off += w * yv[dz][dy][dx];
+                off += w * yv[q][dy][dx];
               }
             }
           }
         }
-        const acc yc = yv[1][1][1];
+        const acc yc = yv[C][1][1];
         const int64_t i = i0 + plane * z;
-        const acc m = SCALED ? yc - off * invd[i] : yc / invd[i] - off;
+        const acc m = SCALED ? yc - off * dinv : yc / dinv - off;
         epi(i, yc, m, pre, part);
-      }
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          yv[0][dy][dx] = yv[1][dy][dx];
-          rv[0][dy][dx] = rv[1][dy][dx];
-          yv[1][dy][dx] = yv[2][dy][dx];
-          rv[1][dy][dx] = rv[2][dy][dx];
-        }
       }
       nxt = after;
       pre = pre_next;
+      dinv = dinv_next;
+    };
+    for (int z = z0; z < z1; z += 3) {
+      step(std::integral_constant<int, 0>{}, z);
+      if (z + 1 < z1) step(std::integral_constant<int, 1>{}, z + 1);
+      if (z + 2 < z1) step(std::integral_constant<int, 2>{}, z + 2);
     }
   }
   finish_reduction<Epi, 64 * TY>(epi, part, rb, slot);
