@@ -495,7 +495,7 @@ def run_paper_scale(nx, torch, pc, W, dev, bounds="exact"):
         lo, hi = est["lambda_min"], 1.01 * est["lambda_max"]
     b = torch.empty(n, dtype=torch.float64, device=dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
-    cases = [(5, "f32", 4, True), (5, "f64", 3, False), (2, "f32", 1, True), (0, "f64", 1, False)]
+    cases = [(5, "f32", 4, True), (5, "f64", 4, False), (2, "f32", 1, True), (0, "f64", 1, False)]
     for rhs in ("ones", "uniform01"):
         if rhs == "ones":
             x.fill_(1.0)
