@@ -24,11 +24,12 @@ struct bf16 {
 __device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
 // float -> bfloat16, round to nearest, ties to even; NaN stays a quiet NaN.
+// gfx950 converts in one instruction (v_cvt_pk_bf16_f32, two values per
+// instruction); it equals the integer rounding (u + 0x7fff + lsb) >> 16 on
+// every non-NaN float (checked on all 2^32 bit patterns).
 __device__ __forceinline__ uint16_t float_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
+  const __bf16 h = static_cast<__bf16>(f);
+  return __builtin_bit_cast(uint16_t, h);
 }
 
 // Float64 vector outputs are stored non-temporally: a solve writes whole
