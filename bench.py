@@ -103,8 +103,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU design "
-                                   "is described but not built)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding over several GPUs "
+                                   "is a design, not implemented)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

@@ -177,3 +177,15 @@ def test_block_size_needs_csr_with_node_rows():
                                            ctypes.byref(hi), None) == 1
     assert lib.pcheb_estimate_bounds_block(ctypes.byref(csr.c), 2, None, 30, ctypes.byref(lo),
                                            ctypes.byref(hi), None) == 1 and "block_size" in pc.pcheb_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with status 2 and a JSON message, before touching a GPU."""
+    import json
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert p.returncode == 2
+    msg = json.loads(p.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
