@@ -189,8 +189,15 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
   using acc = typename Epi::acc;
   static_assert(SCALED || sizeof(acc) == 8, "A_hat products run in double");
   constexpr int W = 64 + 2;
-  __shared__ acc ys[2][TY + 2][W];
-  __shared__ acc rs[2][TY + 2][W];
+  // float64 recurrence steps: the three planes are read from LDS (a ring of
+  // four buffers) instead of being copied into a register ring, whose 108
+  // float64 registers left two wavefronts per SIMD (step 99 -> 87 us on 192^3).
+  // The unscaled product keeps the register ring: its IEEE division holds it
+  // at two wavefronts per SIMD either way, and there the LDS reads cost more.
+  constexpr bool kLdsRing = sizeof(acc) == 8 && SCALED;
+  constexpr int NBUF = kLdsRing ? 4 : 2;
+  __shared__ acc ys[NBUF][TY + 2][W];
+  __shared__ acc rs[NBUF][TY + 2][W];
   const int slot = slot0 + int(blockIdx.y);
   if (bind_slot(in, epi, slot)) return;
   double part[Epi::NV];
@@ -242,8 +249,9 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
     };
     acc yv[3][3][3], rv[3][3][3];
     auto stage = [&](const Vals& v, int ring) {
-      acc(*yb)[W] = ys[k & 1];
-      acc(*rb2)[W] = rs[k & 1];
+      const uint32_t buf = kLdsRing ? (k & 3u) : (k & 1u);
+      acc(*yb)[W] = ys[buf];
+      acc(*rb2)[W] = rs[buf];
       yb[ty + 1][tx + 1] = v.y0;
       rb2[ty + 1][tx + 1] = v.r0;
       if (hy_on) {
@@ -255,12 +263,14 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
         rb2[hx_r][hx_col] = v.r2;
       }
       __syncthreads();
+      if constexpr (!kLdsRing) {
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
+        for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          yv[ring][dy][dx] = yb[ty + dy][tx + dx];
-          rv[ring][dy][dx] = rb2[ty + dy][tx + dx];
+          for (int dx = 0; dx < 3; ++dx) {
+            yv[ring][dy][dx] = yb[ty + dy][tx + dx];
+            rv[ring][dy][dx] = rb2[ty + dy][tx + dx];
+          }
         }
       }
       ++k;
@@ -292,28 +302,51 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
       stage(nxt, (PH + 2) % 3);
       if (own) {
         constexpr int C = (PH + 1) % 3;
-        const acc ri = rv[C][1][1];
-        acc off = acc(0);
+        acc off = acc(0), yc;
+        if constexpr (kLdsRing) {
+          // buffers of the planes below, at and above the point: the last three staged
+          const uint32_t bz[3] = {(k - 3u) & 3u, (k - 2u) & 3u, (k - 1u) & 3u};
+          const acc ri = rs[bz[1]][ty + 1][tx + 1];
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-          const int q = (PH + dz) % 3;
+          for (int dz = 0; dz < 3; ++dz) {
+            const acc(*yq)[W] = ys[bz[dz]];
+            const acc(*rq)[W] = rs[bz[dz]];
 #pragma unroll
-          for (int dy = 0; dy < 3; ++dy) {
+            for (int dy = 0; dy < 3; ++dy) {
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-              if (dz == 1 && dy == 1 && dx == 1) continue;
-              const acc d = ri + rv[q][dy][dx];
-              if constexpr (sizeof(acc) == 4) {
-                off += __builtin_amdgcn_rcpf(d) * yv[q][dy][dx];
-              } else {
+              for (int dx = 0; dx < 3; ++dx) {
+                if (dz == 1 && dy == 1 && dx == 1) continue;
+                const acc d = ri + rq[ty + dy][tx + dx];
                 double w = __builtin_amdgcn_rcp(d);
                 w = fma(fma(-d, w, 1.0), w, w);
-                off += w * yv[q][dy][dx];
+                off += w * yq[ty + dy][tx + dx];
               }
             }
           }
+          yc = ys[bz[1]][ty + 1][tx + 1];
+        } else {
+          const acc ri = rv[C][1][1];
+#pragma unroll
+          for (int dz = 0; dz < 3; ++dz) {
+            const int q = (PH + dz) % 3;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+              for (int dx = 0; dx < 3; ++dx) {
+                if (dz == 1 && dy == 1 && dx == 1) continue;
+                const acc d = ri + rv[q][dy][dx];
+                if constexpr (sizeof(acc) == 4) {
+                  off += __builtin_amdgcn_rcpf(d) * yv[q][dy][dx];
+                } else {  // the unscaled float64 product
+                  double w = __builtin_amdgcn_rcp(d);
+                  w = fma(fma(-d, w, 1.0), w, w);
+                  off += w * yv[q][dy][dx];
+                }
+              }
+            }
+          }
+          yc = yv[C][1][1];
         }
-        const acc yc = yv[C][1][1];
         const int64_t i = i0 + plane * z;
         const acc m = SCALED ? yc - off * dinv : yc / dinv - off;
         epi(i, yc, m, pre, part);
