@@ -58,7 +58,8 @@ typedef enum pcheb_op_kind {
 typedef enum pcheb_precision {
   PCHEB_F64 = 0,            /* p_k(A) recurrence in float64 */
   PCHEB_F32 = 1,            /* matrix values and iterates stored and accumulated in float32 */
-  PCHEB_BF16 = 2            /* matrix values and iterates stored in bfloat16, accumulated in float32 */
+  PCHEB_BF16 = 2            /* matrix values and iterates stored in bfloat16, accumulated in float32;
+                               degree k <= 32 (see pcheb_setup) */
 } pcheb_precision;
 
 /*
@@ -162,7 +163,10 @@ typedef struct pcheb_handle_s* pcheb_handle;
  * one right-hand side.  Synchronises `stream` once.
  * With block_size 3 it also factors the 3x3 diagonal block of every node
  * (second-level preconditioner, see pcheb_params).
- * Errors: INVALID (k out of range, lambda_min <= 0, lambda_min >= lambda_max,
+ * A bfloat16 recurrence (PCHEB_BF16) is refused above k = 32: the rounding of
+ * its stored iterates then costs PCG iterations and moves the solution by more
+ * than 1e-6 relative from the float64 recurrence's on 7-point problems.
+ * Errors: INVALID (k out of range, BF16 with k > 32, lambda_min <= 0, lambda_min >= lambda_max,
  * s < 1, null or inconsistent arrays, unsupported SELL chunk, block_size not
  * 1 or 3, block_size 3 on a stencil, with n % 3 != 0 or with node rows of
  * different patterns), NOT_SPD (diagonal <= 0, a coefficient <= 0, or a node
@@ -218,6 +222,32 @@ const char* pcheb_last_error(void);
 
 /* Device bytes pcheb_setup plus pcg_solve with nrhs right-hand sides will allocate. */
 size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int32_t nrhs);
+
+/*
+ * Device memory.  Every block of device memory the library allocates (a
+ * handle's operator copies and solve workspace, the bound estimators'
+ * workspace, the server's resident groups, right-hand-side and solution
+ * staging and Lanczos start vectors) comes from alloc_fn once it is installed,
+ * so a caller's pool (for example PyTorch's caching allocator) supplies it;
+ * the problem statement of Sec. 1 leaves memory to the caller's environment.
+ *  - alloc_fn(bytes, ctx) returns a block of at least `bytes` bytes on the
+ *    current device, 256-byte aligned and usable from any stream, or NULL (the
+ *    library call then fails with PCHEB_OOM).  It may be called from any host
+ *    thread, including the server's own threads, with that device current.
+ *  - free_fn(ptr, bytes, ctx) takes a block back.  The library calls it only
+ *    once no device work that may use the block is pending (it synchronises the
+ *    device first when a handle, an estimate or a server group releases
+ *    memory), and always with the free_fn and ctx that were installed when the
+ *    block was allocated, even if another allocator has been installed since.
+ *  - Both NULL restores hipMalloc / hipFree for later allocations.  The
+ *    setting is process-wide and is read at each allocation.
+ * Not covered: the small pinned host mirrors of solver states
+ * (hipHostMalloc) and memory the HIP runtime allocates for itself (graphs).
+ * Errors: INVALID if exactly one of the two functions is NULL.
+ */
+typedef void* (*pcheb_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*pcheb_free_fn)(void* ptr, size_t bytes, void* ctx);
+pcheb_status pcheb_set_allocator(pcheb_alloc_fn alloc_fn, pcheb_free_fn free_fn, void* ctx);
 
 /*
  * Extreme Ritz values of nsteps Lanczos steps (classical Gram-Schmidt

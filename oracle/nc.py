@@ -149,11 +149,12 @@ class PCGResult:
 
 
 def pcg(matvec, b: np.ndarray, precond, tol: float, maxit: int, flexible: bool = False,
-        x0: np.ndarray = None) -> PCGResult:
+        x0: np.ndarray = None, progress=None) -> PCGResult:
     """Preconditioned CG (Saad 2003, Alg. 9.1); `precond(r)` returns z = M r.
 
     Per iteration: q = A p, alpha = (r, z)/(p, q), x += alpha p, r -= alpha q, stop test,
-    z = M r, beta, p = z + beta p."""
+    z = M r, beta, p = z + beta p.  `progress(i, relres)`, if given, is called after the
+    residual update of iteration i (reporting only)."""
     n_dot = 0  # counted as in Table 3: (r, z) once, then (p, q), (r, r), (r, z) per iteration
     bnorm = np.sqrt(b @ b)
     if bnorm == 0.0:
@@ -191,6 +192,8 @@ def pcg(matvec, b: np.ndarray, precond, tol: float, maxit: int, flexible: bool =
         rnorm = np.sqrt(r @ r)
         n_dot += 1
         hist.append(rnorm / bnorm)
+        if progress is not None:
+            progress(it, rnorm / bnorm)
         if not np.isfinite(rnorm):
             breakdown = True
             break
@@ -228,7 +231,7 @@ class NCResult:
 
 
 def nc_pcg(rowptr, colind, values, b_hat, lambda_min, lambda_max, k, s=1.001, tol=1e-8,
-           maxit=100000, flexible=False, x0_hat=None) -> NCResult:
+           maxit=100000, flexible=False, x0_hat=None, progress=None) -> NCResult:
     """Solve A_hat x_hat = b_hat by PCG with the degree-k NC preconditioner (Sec. 5 set-up).
 
     The system is Jacobi-scaled, the preconditioner p_k(A) uses the bounds
@@ -241,7 +244,7 @@ def nc_pcg(rowptr, colind, values, b_hat, lambda_min, lambda_max, k, s=1.001, to
     op = CountingOperator(a)
     c = chebyshev_scalars(lambda_min, lambda_max, k, s)
     x0 = None if x0_hat is None else x0_hat / dm
-    res = pcg(op, b, lambda r: chebyshev_apply(op, r, c, k), tol, maxit, flexible, x0)
+    res = pcg(op, b, lambda r: chebyshev_apply(op, r, c, k), tol, maxit, flexible, x0, progress)
     x_hat = dm * res.x
     rt = b - a @ res.x
     rt_hat = b_hat - a_hat @ x_hat

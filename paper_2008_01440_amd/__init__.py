@@ -19,6 +19,7 @@ from ._abi import (
     Operator,
     STATUS,
     Server,
+    TorchCachingAllocator,
     library_path,
     load_library,
     pcg_solve,
@@ -30,6 +31,7 @@ from ._abi import (
     pcheb_footprint_bytes,
     pcheb_last_error,
     pcheb_matvec,
+    pcheb_set_allocator,
     pcheb_setup,
 )
 
@@ -44,6 +46,7 @@ __all__ = [
     "Operator",
     "STATUS",
     "Server",
+    "TorchCachingAllocator",
     "library_path",
     "load_library",
     "pcg_solve",
@@ -55,5 +58,6 @@ __all__ = [
     "pcheb_footprint_bytes",
     "pcheb_last_error",
     "pcheb_matvec",
+    "pcheb_set_allocator",
     "pcheb_setup",
 ]

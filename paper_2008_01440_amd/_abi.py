@@ -113,6 +113,10 @@ class CServeStats(ctypes.Structure):
 
 _lib = None
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_allocator_refs = None  # the installed callbacks, kept alive while the library may call them
+
 
 def library_path() -> str:
     return os.path.join(_PKG, _LIB_NAME)
@@ -144,6 +148,7 @@ def load_library():
     lib.pcheb_estimate_bounds_pdacg.argtypes = [ctypes.POINTER(COperator), vp, i32, f64, i32, ctypes.POINTER(f64),
                                                 ctypes.POINTER(f64), ctypes.POINTER(i32), ctypes.POINTER(f64), vp]
     lib.pcheb_fill_uniform.argtypes = [vp, i64, ctypes.c_uint64, f64, f64, vp]
+    lib.pcheb_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.pserve_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(vp)]
     lib.pserve_submit.argtypes = [vp, ctypes.POINTER(CServeRequest), u64p]
@@ -153,7 +158,7 @@ def load_library():
     lib.pserve_get_stats.argtypes = [vp, ctypes.POINTER(CServeStats)]
     lib.pserve_destroy.argtypes = [vp]
     for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
-                 "pcheb_estimate_bounds", "pcheb_estimate_bounds_block", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
+                 "pcheb_set_allocator", "pcheb_estimate_bounds", "pcheb_estimate_bounds_block", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
                  "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -357,6 +362,57 @@ def pcheb_fill_uniform(v, seed: int, lo: float = 0.0, hi: float = 1.0, stream=No
     """v[i] = lo + (hi - lo) * U_i from the SplitMix64 stream of `seed` (float64 device vector)."""
     _check(load_library().pcheb_fill_uniform(_dptr(v, "float64"), v.numel(), seed & 0xFFFFFFFFFFFFFFFF, lo, hi,
                                              _stream(stream)))
+
+
+def pcheb_set_allocator(allocator=None):
+    """Install `allocator` (an object with alloc(nbytes) -> int device pointer, 0 on failure,
+    and free(ptr, nbytes)) as the source of all the library's device memory; None restores
+    hipMalloc / hipFree.  Callbacks of an earlier allocator stay alive: blocks it handed out
+    are returned to it."""
+    global _allocator_refs
+    lib = load_library()
+    if allocator is None:
+        _check(lib.pcheb_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return int(allocator.alloc(int(nbytes))) or None
+        except Exception:  # noqa: BLE001 - reported to the library as a failed allocation
+            return None
+
+    def _free(ptr, nbytes, _ctx):
+        allocator.free(int(ptr), int(nbytes))
+
+    refs = (ALLOC_FN(_alloc), FREE_FN(_free), allocator)
+    _check(lib.pcheb_set_allocator(refs[0], refs[1], None))
+    _allocator_refs = (refs, _allocator_refs)
+
+
+class TorchCachingAllocator:
+    """Device memory for the library from PyTorch's caching allocator (torch.cuda.caching_allocator_alloc
+    on the current device and stream), with counts of the blocks handed out and returned."""
+
+    def __init__(self):
+        self.live = {}
+        self.n_alloc = 0
+        self.n_free = 0
+        self.bytes_alloc = 0
+
+    def alloc(self, nbytes):
+        import torch
+        ptr = torch.cuda.caching_allocator_alloc(nbytes, device=torch.cuda.current_device())
+        self.live[ptr] = nbytes
+        self.n_alloc += 1
+        self.bytes_alloc += nbytes
+        return ptr
+
+    def free(self, ptr, nbytes):
+        import torch
+        if self.live.pop(ptr, None) is None:
+            raise RuntimeError(f"free of a block this allocator did not hand out: {ptr:#x}")
+        self.n_free += 1
+        torch.cuda.caching_allocator_delete(ptr)
 
 
 def _stats_dict(st: CStats, status) -> dict:

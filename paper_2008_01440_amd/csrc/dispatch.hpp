@@ -41,7 +41,9 @@ inline StencilGrid stencil_grid(const pcheb_operator& op, int rows, int zc) {
 }
 
 // Tv: value type of CSR/SELL arrays (float64 for A_hat; storage type for D^-1 A_hat).
-// The launch covers solve slots slot0 .. slot0 + nslots - 1 (grid dimension y).
+// The launch covers solve slots slot0 .. slot0 + nslots - 1: one slot per grid row
+// (dimension y) for the stencils; CSR and SELL launches of several slots read the
+// matrix once for every kMultiSlots of them (k_csr_multi, k_sell_multi).
 template <bool SCALED, class Tv, class In, class Epi>
 void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Epi epi, int slot0, int nslots,
                hipStream_t s) {
@@ -74,12 +76,21 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     const int64_t rows = int64_t(kBlock / kWave) * (wide ? PW * (kWave / L) : kWave / L);                  \
     const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);                                              \
     grid = round_grid(tiles);                                                                              \
-    if (wide)                                                                                              \
-      k_csr<L, PW, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \
-                                                                     h.n, uint32_t(tiles), h.rb(), slot0); \
-    else                                                                                                   \
-      k_csr<L, 1, Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, \
-                                                                     h.n, uint32_t(tiles), h.rb(), slot0); \
+    if (nslots > 1) {                                                                                      \
+      const dim3 mg(grid, (nslots + kMultiSlots - 1) / kMultiSlots);                                       \
+      if (wide)                                                                                            \
+        k_csr_multi<L, PW, Tv, In, Epi><<<mg, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n,  \
+                                                             uint32_t(tiles), h.rb(), slot0, nslots);      \
+      else                                                                                                 \
+        k_csr_multi<L, 1, Tv, In, Epi><<<mg, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n,   \
+                                                            uint32_t(tiles), h.rb(), slot0, nslots);       \
+    } else if (wide) {                                                                                     \
+      k_csr<L, PW, Tv, In, Epi><<<dim3(grid, 1), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi,    \
+                                                                h.n, uint32_t(tiles), h.rb(), slot0);      \
+    } else {                                                                                               \
+      k_csr<L, 1, Tv, In, Epi><<<dim3(grid, 1), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi,     \
+                                                               h.n, uint32_t(tiles), h.rb(), slot0);       \
+    }                                                                                                      \
     break;                                                                                                 \
   }
       switch (h.lanes) {
@@ -96,9 +107,14 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     case PCHEB_OP_SELL: {
       const uint64_t tiles = uint64_t((h.nchunks + 3) / 4);
       grid = round_grid(tiles);
-      k_sell<Tv, In, Epi><<<dim3(grid, nslots), kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val,
-                                                                h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(),
-                                                                slot0);
+      if (nslots > 1)
+        k_sell_multi<Tv, In, Epi><<<dim3(grid, (nslots + kMultiSlots - 1) / kMultiSlots), kBlock, 0, s>>>(
+            h.sell_ptr, h.sell_len, h.sell_col, sell_val, h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(), slot0,
+            nslots);
+      else
+        k_sell<Tv, In, Epi><<<dim3(grid, 1), kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val,
+                                                             h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(),
+                                                             slot0);
       break;
     }
     default:

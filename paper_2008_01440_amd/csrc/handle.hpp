@@ -25,10 +25,24 @@ void set_last_error(const std::string& msg);
 
 #define PCHEB_HIP_CHECK(expr) ::pcheb::check_hip((expr), #expr)
 
+// A block of device memory and the function that returns it (null: hipFree).
 struct DeviceBuffer {
   void* ptr = nullptr;
   size_t bytes = 0;
+  pcheb_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
 };
+
+// Device memory from the allocator installed with pcheb_set_allocator, or hipMalloc
+// when none is; throws OOM / HIP / INVALID (a misaligned block).
+DeviceBuffer device_alloc(size_t bytes);
+// Returns a block to whoever allocated it.  Blocks from a caller's allocator may be
+// reused at once, so the caller of this function must have ensured that no device
+// work still uses the block (device_free_all does so for a whole list).
+void device_free(DeviceBuffer& b);
+// Frees every block of the list, after synchronising the device if any of them goes
+// back to a caller's allocator (hipFree waits by itself).
+void device_free_all(std::vector<DeviceBuffer>& list);
 
 struct Handle {
   pcheb_operator op{};

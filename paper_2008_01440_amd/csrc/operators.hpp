@@ -508,6 +508,213 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
   finish_reduction(epi, part, rb, slot);
 }
 
+// ------------------------------------------------------------------ several right-hand sides, matrix read once
+//
+// k_csr_multi and k_sell_multi: a block serves kMultiSlots consecutive solve
+// slots (slot0 + blockIdx.y * kMultiSlots + k, k < kMultiSlots, up to slot0 +
+// nslots), reads every column index and value of its rows once and applies it
+// to each active slot's vector.  Tiles, rows, lanes and the order of every
+// slot's sums are those of the single-slot kernels, and a slot's block
+// partials go to the same places, so each slot's results are bitwise those of
+// k_csr / k_sell alone; only the matrix traffic is shared.  Slots whose solve
+// has finished are skipped.
+constexpr int kMultiSlots = 4;
+
+template <class In, class Epi>
+struct SlotSet {
+  In in[kMultiSlots];
+  Epi epi[kMultiSlots];
+  bool on[kMultiSlots];
+  // true if no slot of the block is active
+  __device__ __forceinline__ bool bind(const In& in0, const Epi& epi0, int first, int last) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kMultiSlots; ++k) {
+      in[k] = in0;
+      epi[k] = epi0;
+      on[k] = first + k < last && !bind_slot(in[k], epi[k], first + k);
+      any = any || on[k];
+    }
+    return !any;
+  }
+};
+
+template <int LANES, int PASSES, class Tv, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_csr_multi(const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const Tv* __restrict__ val,
+                                                      In in, Epi epi, int64_t n, uint32_t ntiles, ReduceBuf rb,
+                                                      int slot0, int nslots) {
+  using acc = typename Epi::acc;
+  constexpr int NS = kMultiSlots;
+  const int first = slot0 + int(blockIdx.y) * NS;
+  SlotSet<In, Epi> ss;
+  if (ss.bind(in, epi, first, slot0 + nslots)) return;
+  double part[NS][Epi::NV];
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int v = 0; v < Epi::NV; ++v) part[k][v] = 0.0;
+  constexpr int kGroups = kWave / LANES;
+  constexpr int kRows = PASSES * kGroups;
+  const int lane = int(threadIdx.x) % kWave;
+  const int wave = int(threadIdx.x) / kWave;
+  const int g = lane % LANES;
+  const int grp = lane / LANES;
+  XcdTiles tiles(ntiles);
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const int64_t base = (int64_t(t) * (kBlock / kWave) + wave) * kRows;
+    if (base >= n) continue;
+    const int64_t myrow = base + lane;
+    const int32_t rb_lane = rowptr[myrow < n ? myrow : n];
+    const int32_t re_lane = rowptr[myrow + 1 < n ? myrow + 1 : n];
+    const bool has_row = lane < kRows && myrow < n;
+    typename Epi::Pre pre[NS];
+    acc yi[NS], mine[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      pre[k] = typename Epi::Pre{};
+      yi[k] = acc(0);
+      mine[k] = acc(0);
+      if (ss.on[k] && has_row) {
+        pre[k] = ss.epi[k].load(myrow);
+        yi[k] = ss.in[k].ld(myrow);
+      }
+    }
+    if constexpr (PASSES > 1 && PASSES <= 8) {
+      acc sums[PASSES][NS];
+      int32_t rb_it[PASSES], re_it[PASSES];
+#pragma unroll
+      for (int it = 0; it < PASSES; ++it) {
+        const int r = it * kGroups + grp;
+        rb_it[it] = __shfl(rb_lane, r, kWave);
+        re_it[it] = __shfl(re_lane, r, kWave);
+      }
+#pragma unroll
+      for (int it = 0; it < PASSES; ++it) {
+        const int32_t j0 = rb_it[it] + g, j1 = j0 + LANES;
+        const bool ok0 = j0 < re_it[it], ok1 = j1 < re_it[it];
+        const int32_t c0 = ok0 ? j0 : 0, c1 = ok1 ? j1 : 0;
+        const acc a0 = acc(Store<Tv>::ld(val, c0)), a1 = acc(Store<Tv>::ld(val, c1));
+        const int32_t x0 = col[c0], x1 = col[c1];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          acc sum = acc(0);
+          if (ss.on[k]) {
+            const acc v0 = a0 * ss.in[k].ld(x0);
+            const acc v1 = a1 * ss.in[k].ld(x1);
+            sum += ok0 ? v0 : acc(0);
+            sum += ok1 ? v1 : acc(0);
+          }
+          sums[it][k] = sum;
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < PASSES; ++it) {
+        for (int32_t j = rb_it[it] + g + 2 * LANES; j < re_it[it]; j += LANES) {
+          const acc a = acc(Store<Tv>::ld(val, j));
+          const int32_t x = col[j];
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (ss.on[k]) sums[it][k] += a * ss.in[k].ld(x);
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          acc sum = sums[it][k];
+#pragma unroll
+          for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+          const acc v = __shfl(sum, (lane % kGroups) * LANES, kWave);
+          if (lane / kGroups == it) mine[k] = v;
+        }
+      }
+    } else {
+      for (int it = 0; it < PASSES; ++it) {
+        const int r = it * kGroups + grp;
+        const int32_t b = __shfl(rb_lane, r, kWave), e = __shfl(re_lane, r, kWave);
+        acc sums[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sums[k] = acc(0);
+        for (int32_t j = b + g; j < e; j += LANES) {
+          const acc a = acc(Store<Tv>::ld(val, j));
+          const int32_t x = col[j];
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if (ss.on[k]) sums[k] += a * ss.in[k].ld(x);
+        }
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          acc sum = sums[k];
+#pragma unroll
+          for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+          const acc v = __shfl(sum, (lane % kGroups) * LANES, kWave);
+          if (lane / kGroups == it) mine[k] = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (ss.on[k] && has_row) ss.epi[k](myrow, yi[k], mine[k], pre[k], part[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+    if (ss.on[k]) finish_reduction(ss.epi[k], part[k], rb, first + k);
+}
+
+template <class Tv, class In, class Epi>
+__global__ __launch_bounds__(kBlock) void k_sell_multi(const int64_t* __restrict__ chunk_ptr,
+                                                       const int32_t* __restrict__ chunk_len,
+                                                       const int32_t* __restrict__ col, const Tv* __restrict__ val,
+                                                       const int32_t* __restrict__ perm, In in, Epi epi, int64_t n,
+                                                       uint32_t ntiles, ReduceBuf rb, int slot0, int nslots) {
+  using acc = typename Epi::acc;
+  constexpr int NS = kMultiSlots;
+  const int first = slot0 + int(blockIdx.y) * NS;
+  SlotSet<In, Epi> ss;
+  if (ss.bind(in, epi, first, slot0 + nslots)) return;
+  double part[NS][Epi::NV];
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int v = 0; v < Epi::NV; ++v) part[k][v] = 0.0;
+  const int lane = threadIdx.x % kWave;
+  XcdTiles tiles(ntiles);
+  for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
+    const int64_t chunk = int64_t(t) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t pos = chunk * kWave + lane;
+    if (chunk * kWave >= n) continue;
+    const int64_t base = chunk_ptr[chunk];
+    const int32_t len = chunk_len[chunk];
+    const bool has_row = pos < n;
+    const int64_t row = has_row ? (perm ? int64_t(perm[pos]) : pos) : 0;
+    typename Epi::Pre pre[NS];
+    acc yi[NS], sum[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      pre[k] = typename Epi::Pre{};
+      yi[k] = acc(0);
+      sum[k] = acc(0);
+      if (ss.on[k] && has_row) {
+        pre[k] = ss.epi[k].load(row);
+        yi[k] = ss.in[k].ld(row);
+      }
+    }
+#pragma unroll 4
+    for (int32_t j = 0; j < len; ++j) {
+      const int64_t e = base + int64_t(j) * kWave + lane;
+      const acc a = acc(Store<Tv>::ld(val, e));
+      const int32_t x = col[e];
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (ss.on[k]) sum[k] += a * ss.in[k].ld(x);
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (ss.on[k] && has_row) ss.epi[k](row, yi[k], sum[k], pre[k], part[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+    if (ss.on[k]) finish_reduction(ss.epi[k], part[k], rb, first + k);
+}
+
 // ------------------------------------------------------------------ input functors
 
 template <class T>

@@ -89,6 +89,7 @@ struct Group {
   hipStream_t stream = nullptr;
   double* X = nullptr;  // cap vectors, stride ldw (solutions)
   double* B = nullptr;  // cap vectors, stride ldw (right-hand sides)
+  DeviceBuffer xb, bb;  // the blocks of X and B
   int cap = 0;
   std::vector<uint64_t> slot_req;       // request id, 0 = free
   std::vector<int64_t> slot_since;      // launch sequence number when the slot joined
@@ -172,8 +173,10 @@ static void destroy_group(Group& g) {
     if (e) (void)hipEventDestroy(e);
   if (g.poll) (void)hipHostFree(g.poll);
   if (g.fin) (void)hipHostFree(g.fin);
-  if (g.X) (void)hipFree(g.X);
-  if (g.B) (void)hipFree(g.B);
+  std::vector<DeviceBuffer> blocks{g.xb, g.bb};
+  device_free_all(blocks);
+  g.xb = g.bb = DeviceBuffer{};
+  g.X = g.B = nullptr;
   destroy_handle(g.h);
   g.h = nullptr;
   if (g.stream) (void)hipStreamDestroy(g.stream);
@@ -189,12 +192,11 @@ static std::unique_ptr<Group> create_group(Server& sv, const pserve_request& r) 
     PCHEB_HIP_CHECK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     double lmin = r.lambda_min, lmax = r.lambda_max;
     if (!(lmax > 0)) {
-      double* v0 = nullptr;
-      PCHEB_HIP_CHECK(hipMalloc(&v0, size_t(r.op.n) * sizeof(double)));
+      std::vector<DeviceBuffer> start{device_alloc(size_t(r.op.n) * sizeof(double))};
+      double* v0 = static_cast<double*>(start[0].ptr);
       launch_fill_uniform(v0, r.op.n, 7, 0.5, 1.5, g->stream);  // Lanczos start: U[0.5, 1.5), seed 7
       const pcheb_status e = pcheb_estimate_bounds(&r.op, v0, 30, &lmin, &lmax, g->stream);
-      (void)hipStreamSynchronize(g->stream);
-      (void)hipFree(v0);
+      device_free_all(start);
       if (e != PCHEB_OK) fail(e, std::string("bound estimate: ") + last_error_cstr());
       lmax *= 1.01;
     }
@@ -202,8 +204,10 @@ static std::unique_ptr<Group> create_group(Server& sv, const pserve_request& r) 
     g->h = create_handle(&r.op, &p, g->stream);
     ensure_workspace(*g->h, g->cap, g->stream);
     const size_t lw = size_t(g->h->ldw) * size_t(g->cap);
-    PCHEB_HIP_CHECK(hipMalloc(&g->X, lw * sizeof(double)));
-    PCHEB_HIP_CHECK(hipMalloc(&g->B, lw * sizeof(double)));
+    g->xb = device_alloc(lw * sizeof(double));
+    g->X = static_cast<double*>(g->xb.ptr);
+    g->bb = device_alloc(lw * sizeof(double));
+    g->B = static_cast<double*>(g->bb.ptr);
     PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&g->poll), size_t(g->cap) * sizeof(DevState),
                                   hipHostMallocDefault));
     PCHEB_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&g->fin), size_t(g->cap) * sizeof(DevState),

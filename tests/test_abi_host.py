@@ -22,13 +22,15 @@ pytestmark = pytest.mark.skipif(not os.path.exists(_abi.library_path()), reason=
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?!typedef\b)(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", text,
+                                 flags=re.M)))
 
 
 def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
-                 "pcheb_footprint_bytes", "pcheb_estimate_bounds", "pcheb_estimate_bounds_pdacg",
+                 "pcheb_footprint_bytes", "pcheb_set_allocator", "pcheb_estimate_bounds",
+                 "pcheb_estimate_bounds_pdacg",
                  "pcheb_estimate_bounds_block", "pserve_create",
                  "pserve_submit", "pserve_poll",
                  "pserve_wait", "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
@@ -83,6 +85,7 @@ def _setup_status(op, k=5, lmin=0.1, lmax=1.9, s=1.0, prec=0, form=0, block_size
     (dict(s=0.99), "theta_scale"), (dict(prec=7), "precision"), (dict(form=2), "form"),
     (dict(k=5, form=1), "Newton"), (dict(k=6, form=1), "Newton"), (dict(k=7, form=1, prec=2), "Newton"),
     (dict(block_size=2), "block_size"), (dict(block_size=3), "block_size"), (dict(block_size=-1), "block_size"),
+    (dict(k=33, prec=2), "bfloat16"), (dict(k=100, prec=2), "bfloat16"),
 ])
 def test_setup_rejects_bad_parameters(kw, what):
     assert _setup_status(pc.Operator.stencil7(4), **kw) == 1
@@ -189,3 +192,14 @@ def test_bench_refuses_more_than_one_gpu():
     assert p.returncode == 2
     msg = json.loads(p.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_set_allocator_needs_both_functions():
+    lib = pc.load_library()
+    alloc = _abi.ALLOC_FN(lambda nbytes, ctx: None)
+    free = _abi.FREE_FN(lambda ptr, nbytes, ctx: None)
+    assert lib.pcheb_set_allocator(alloc, _abi.FREE_FN(), None) == 1 and "both" in pc.pcheb_last_error()
+    assert lib.pcheb_set_allocator(_abi.ALLOC_FN(), free, None) == 1
+    assert lib.pcheb_set_allocator(_abi.ALLOC_FN(), _abi.FREE_FN(), None) == 0  # hipMalloc / hipFree again
+    pc.pcheb_set_allocator(None)
+
