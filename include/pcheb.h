@@ -242,7 +242,8 @@ size_t pcheb_footprint_bytes(const pcheb_operator* A, const pcheb_params* p, int
  *  - Both NULL restores hipMalloc / hipFree for later allocations.  The
  *    setting is process-wide and is read at each allocation.
  * Not covered: the small pinned host mirrors of solver states
- * (hipHostMalloc) and memory the HIP runtime allocates for itself (graphs).
+ * (hipHostMalloc) and memory the HIP runtime allocates for itself (graphs,
+ * the fixed scratch array of pcheb_estimate_bounds_noalloc).
  * Errors: INVALID if exactly one of the two functions is NULL.
  */
 typedef void* (*pcheb_alloc_fn)(size_t bytes, void* ctx);
@@ -263,6 +264,29 @@ pcheb_status pcheb_set_allocator(pcheb_alloc_fn alloc_fn, pcheb_free_fn free_fn,
  */
 pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
                                    double* lambda_min, double* lambda_max, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture
+ * around the call, tight serving loops, harnesses that forbid hipMalloc):
+ * pcheb_estimate_bounds, with the same arguments, results (bit for bit) and
+ * errors, that allocates nothing.  Its workspace - the Lanczos basis, the
+ * vectors, the operator's diagonal and the reduction partials - lives in a
+ * fixed device array of PCHEB_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it has run this call on, until the process ends; the call
+ * takes it over without clearing it first (nothing in it is read before it is
+ * written).  The workspace is
+ *   8 * ((nsteps + 1) * round_up(n, 2) + (2 + d) * n + 3 * nsteps + 3) + 524288
+ * bytes plus at most 2 KiB of alignment, with d = 0 for STENCIL7, 1 for CSR or
+ * SELL and 2 for STENCIL27H (nsteps capped at n): with 30 steps, up to about
+ * 500,000 unknowns of a 7-point grid (79^3).  A larger operator returns INVALID before
+ * any work is enqueued.  Every call on a device uses that device's one array:
+ * calls that overlap on one GPU (from two host threads, or on two streams
+ * without ordering between them) race and give wrong results.  Synchronises
+ * `stream` as pcheb_estimate_bounds does.
+ */
+#define PCHEB_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+pcheb_status pcheb_estimate_bounds_noalloc(const pcheb_operator* A, const double* v0, int32_t nsteps,
+                                           double* lambda_min, double* lambda_max, hipStream_t stream);
 
 /*
  * As pcheb_estimate_bounds, for the operator the preconditioner with first-level

@@ -26,6 +26,7 @@ from ._abi import (
     pcheb_apply,
     pcheb_destroy,
     pcheb_estimate_bounds,
+    pcheb_estimate_bounds_noalloc,
     pcheb_estimate_bounds_pdacg,
     pcheb_fill_uniform,
     pcheb_footprint_bytes,
@@ -53,6 +54,7 @@ __all__ = [
     "pcheb_apply",
     "pcheb_destroy",
     "pcheb_estimate_bounds",
+    "pcheb_estimate_bounds_noalloc",
     "pcheb_estimate_bounds_pdacg",
     "pcheb_fill_uniform",
     "pcheb_footprint_bytes",

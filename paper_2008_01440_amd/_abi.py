@@ -143,6 +143,8 @@ def load_library():
     lib.pcheb_footprint_bytes.restype = ctypes.c_size_t
     lib.pcheb_estimate_bounds.argtypes = [ctypes.POINTER(COperator), vp, i32, ctypes.POINTER(f64),
                                           ctypes.POINTER(f64), vp]
+    lib.pcheb_estimate_bounds_noalloc.argtypes = [ctypes.POINTER(COperator), vp, i32, ctypes.POINTER(f64),
+                                                  ctypes.POINTER(f64), vp]
     lib.pcheb_estimate_bounds_block.argtypes = [ctypes.POINTER(COperator), i32, vp, i32, ctypes.POINTER(f64),
                                                 ctypes.POINTER(f64), vp]
     lib.pcheb_estimate_bounds_pdacg.argtypes = [ctypes.POINTER(COperator), vp, i32, f64, i32, ctypes.POINTER(f64),
@@ -158,7 +160,7 @@ def load_library():
     lib.pserve_get_stats.argtypes = [vp, ctypes.POINTER(CServeStats)]
     lib.pserve_destroy.argtypes = [vp]
     for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
-                 "pcheb_set_allocator", "pcheb_estimate_bounds", "pcheb_estimate_bounds_block", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
+                 "pcheb_set_allocator", "pcheb_estimate_bounds", "pcheb_estimate_bounds_noalloc", "pcheb_estimate_bounds_block", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
                  "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -341,6 +343,15 @@ def pcheb_estimate_bounds(op: Operator, v0, nsteps: int = 30, stream=None, block
     else:
         _check(load_library().pcheb_estimate_bounds_block(ctypes.byref(op.c), int(block_size), _dptr(v0, "float64"),
                                                           nsteps, ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
+    return lo.value, hi.value
+
+
+def pcheb_estimate_bounds_noalloc(op: Operator, v0, nsteps: int = 30, stream=None):
+    """pcheb_estimate_bounds without device allocation: the workspace is the library's fixed
+    per-device scratch array (INVALID when the operator needs more than it holds)."""
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().pcheb_estimate_bounds_noalloc(ctypes.byref(op.c), _dptr(v0, "float64"), nsteps,
+                                                        ctypes.byref(lo), ctypes.byref(hi), _stream(stream)))
     return lo.value, hi.value
 
 

@@ -23,10 +23,21 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "dispatch.hpp"
 #include "handle.hpp"
+
+// Workspace of pcheb_estimate_bounds_noalloc: a fixed array in device memory
+// that every call on a device shares (the code object holds one copy per
+// device until the process ends).  In host code `scratch` names a host-side
+// stand-in, so it is never passed to a kernel or a copy: the device address
+// comes from hipGetSymbolAddress (scratch_on_current_device).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace pcheb {
 
@@ -677,10 +688,12 @@ void estimator_setup(Handle& h, const pcheb_operator* A, const double* v0, hipSt
 
 template <class F>
 pcheb_status run_estimator(const pcheb_operator* A, const double* v0, hipStream_t stream, F&& body,
-                           int block_size = 1) {
+                           int block_size = 1, char* arena = nullptr, size_t arena_cap = 0) {
   try {
     set_last_error("");
     Handle h;
+    h.arena = arena;
+    h.arena_cap = arena_cap;
     try {
       estimator_setup(h, A, v0, stream, block_size);
       body(h);
@@ -701,7 +714,88 @@ pcheb_status run_estimator(const pcheb_operator* A, const double* v0, hipStream_
   }
 }
 
+// ------------------------------------------------------------------ allocation-free Lanczos
+//
+// Workspace of pcheb_estimate_bounds_noalloc: `scratch` (file scope, above);
+// host code takes its device address from hipGetSymbolAddress, once per device.
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;  // device -> address of that device's copy of `scratch`
+
+char* scratch_on_current_device() {
+  int dev = 0;
+  PCHEB_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    fail(PCHEB_HIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = static_cast<char*>(p);
+  return static_cast<char*>(p);
+}
+
+// Bytes the estimator's set-up (point scaling, F64) and nsteps Lanczos steps
+// take from an arena, in the order they are carved (each piece 256-byte aligned).
+size_t lanczos_arena_bytes(const pcheb_operator& A, int nsteps) {
+  const int64_t n = A.n;
+  const int64_t m = std::min<int64_t>(nsteps, n);
+  const int64_t ldv = (n + 1) / 2 * 2;
+  size_t total = 0;
+  auto piece = [&](size_t b) { total = (total + 255) / 256 * 256 + b; };
+  piece(sizeof(int));  // NOT_SPD flag
+  if (A.kind == PCHEB_OP_CSR || A.kind == PCHEB_OP_SELL) piece(size_t(n) * 8);  // D^-1
+  if (A.kind == PCHEB_OP_STENCIL27H) {
+    piece(size_t(n) * 8);  // D^-1
+    piece(size_t(n) * 8);  // 1 / (2 kappa)
+  }
+  piece(size_t(m + 1) * size_t(ldv) * 8);  // basis
+  piece(size_t(n) * 8);                    // w
+  piece(size_t(n) * 8);                    // D^-1/2
+  piece(size_t(kCols) * kLzGrid * 8);      // partial sums
+  piece(size_t(3 * m + 3) * 8);            // coefficients, alpha, beta, 1/beta, ||v0||
+  return total;
+}
+
 }  // namespace
+
+extern "C" pcheb_status pcheb_estimate_bounds_noalloc(const pcheb_operator* A, const double* v0, int32_t nsteps,
+                                                      double* lambda_min, double* lambda_max, hipStream_t stream) {
+  if (!lambda_min || !lambda_max || !A) {
+    set_last_error("null argument");
+    return PCHEB_INVALID;
+  }
+  if (v0 && reinterpret_cast<uintptr_t>(v0) % 16 != 0) {
+    set_last_error("v0 must be 16-byte aligned");
+    return PCHEB_INVALID;
+  }
+  if (nsteps < 1 || nsteps > 1000) {
+    set_last_error("nsteps must be in [1, 1000]");
+    return PCHEB_INVALID;
+  }
+  if (A->n <= 0) {
+    set_last_error("n must be positive");
+    return PCHEB_INVALID;
+  }
+  const size_t need = lanczos_arena_bytes(*A, nsteps);
+  if (need > kNoAllocScratchBytes) {
+    set_last_error("needs " + std::to_string(need) + " bytes of workspace; the allocation-free estimator has " +
+                   std::to_string(kNoAllocScratchBytes));
+    return PCHEB_INVALID;
+  }
+  char* base = nullptr;
+  try {
+    base = scratch_on_current_device();
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.status;
+  }
+  return run_estimator(
+      A, v0, stream, [&](Handle& h) { lanczos(h, v0, nsteps, lambda_min, lambda_max, stream); }, 1, base,
+      kNoAllocScratchBytes);
+}
 
 extern "C" pcheb_status pcheb_estimate_bounds(const pcheb_operator* A, const double* v0, int32_t nsteps,
                                               double* lambda_min, double* lambda_max, hipStream_t stream) {

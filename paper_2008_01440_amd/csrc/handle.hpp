@@ -108,6 +108,13 @@ struct Handle {
   std::vector<DeviceBuffer> owned;     // operator data
   std::vector<DeviceBuffer> owned_ws;  // solve workspace
 
+  // When set, dev_alloc carves 256-byte aligned pieces from this caller-provided
+  // device range instead of allocating (nothing is freed back; the range is
+  // reused by the next handle that gets it).
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  size_t arena_used = 0;
+
   ReduceBuf rb() const { return ReduceBuf{partials}; }
 };
 

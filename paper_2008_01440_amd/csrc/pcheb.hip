@@ -98,7 +98,16 @@ static void* alloc_into(std::vector<DeviceBuffer>& list, size_t bytes) {
   return list.back().ptr;
 }
 
-void* dev_alloc(Handle& h, size_t bytes) { return alloc_into(h.owned, bytes); }
+void* dev_alloc(Handle& h, size_t bytes) {
+  if (h.arena) {
+    const size_t off = (h.arena_used + 255) / 256 * 256;
+    if (bytes > h.arena_cap || off > h.arena_cap - bytes)
+      fail(PCHEB_INVALID, "workspace exceeds the " + std::to_string(h.arena_cap) + "-byte scratch");
+    h.arena_used = off + bytes;
+    return h.arena + off;
+  }
+  return alloc_into(h.owned, bytes);
+}
 
 static void drop_graph(Handle& h) {
   if (h.graph_exec) (void)hipGraphExecDestroy(h.graph_exec);

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     fns = declared_functions()
     for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
                  "pcheb_footprint_bytes", "pcheb_set_allocator", "pcheb_estimate_bounds",
-                 "pcheb_estimate_bounds_pdacg",
+                 "pcheb_estimate_bounds_noalloc", "pcheb_estimate_bounds_pdacg",
                  "pcheb_estimate_bounds_block", "pserve_create",
                  "pserve_submit", "pserve_poll",
                  "pserve_wait", "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
@@ -203,3 +203,17 @@ def test_set_allocator_needs_both_functions():
     assert lib.pcheb_set_allocator(_abi.ALLOC_FN(), _abi.FREE_FN(), None) == 0  # hipMalloc / hipFree again
     pc.pcheb_set_allocator(None)
 
+
+def test_noalloc_estimator_argument_checks():
+    """The allocation-free estimator refuses bad arguments and operators whose workspace exceeds its
+    fixed scratch before any device work: 80^3 7-point with 30 steps needs
+    8 (31 * 512000 + 2 * 512000 + 93) + 524288 bytes > 128 MiB."""
+    lib = pc.load_library()
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    call = lambda op, steps, v0=None: lib.pcheb_estimate_bounds_noalloc(
+        ctypes.byref(op.c) if op else None, v0, steps, ctypes.byref(lo), ctypes.byref(hi), None)
+    assert call(None, 30) == 1 and "null" in pc.pcheb_last_error()
+    assert call(pc.Operator.stencil7(4), 0) == 1 and "nsteps" in pc.pcheb_last_error()
+    assert call(pc.Operator.stencil7(4), 30, v0=8) == 1 and "aligned" in pc.pcheb_last_error()
+    assert call(pc.Operator.stencil7(80), 30) == 1 and "workspace" in pc.pcheb_last_error()
+    assert call(pc.Operator.stencil7(79), 1001) == 1 and "nsteps" in pc.pcheb_last_error()

@@ -1,7 +1,8 @@
 """All of the library's device memory through a caller's allocator (pcheb_set_allocator):
 counting callbacks backed by PyTorch's caching allocator see every block of a bound
 estimate, a set-up and solve, a served request and the releases; the device's free
-memory drops by no more than the caller's pool grows; and every block comes back."""
+memory drops by no more than the caller's pool grows; every block comes back; and the
+allocation-free estimator calls the allocator not at all."""
 
 import pytest
 
@@ -76,6 +77,12 @@ def test_every_device_block_goes_through_the_allocator(pc):
         assert out["status"] == "OK", out
         assert al.n_alloc > before + 5
         assert not al.live and al.n_alloc == al.n_free, (al.n_alloc, al.n_free)
+
+        # the allocation-free estimator takes nothing from the allocator
+        before = al.n_alloc
+        small = pc.Operator.stencil7(40)
+        pc.pcheb_estimate_bounds_noalloc(small, torch.ones(40 ** 3, dtype=torch.float64, device=DEV), 30)
+        assert al.n_alloc == before
     finally:
         pc.pcheb_set_allocator(None)
     # hipMalloc again
