@@ -68,26 +68,30 @@ static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T*
   // most 2048 threads and 160 KiB of LDS), each z range at least 4 S planes deep
   constexpr int RX = 64 + 2 * S, NP = RX * (TY + 2 * S);
   constexpr int kLds = sizeof(T) < 8 ? (NP + 2 * (RX + 1)) * ((3 * S) % 2 == 0 ? 3 * S + 1 : 3 * S) * 4
-                                     : S * 2 * NP * int(sizeof(typename Store<T>::acc));
+                                     : S * 2 * (NP + 2 * (RX + 1)) * 8;
   constexpr int kPerCu = std::max(1, std::min(2048 / NT, 163840 / kLds));
   const uint32_t target = 256u * kPerCu;
   const int max_chunks = std::max(1, op.nz / (4 * S));
-  const int chunks = std::max(1, std::min<int>(max_chunks, int((target + xy - 1) / xy)));
+  int chunks = std::max(1, std::min<int>(max_chunks, int((target + xy - 1) / xy)));
+  {
+    // the buffer-addressed passes cover a tile's zc + 2 S + 1 planes with one descriptor
+    const int64_t plane_bytes = int64_t(op.nx) * op.ny * int64_t(sizeof(T));
+    const int64_t zc_max = kMaxSpanBytes / plane_bytes - 2 * S - 1;
+    if (zc_max >= 1) chunks = std::max<int>(chunks, int((op.nz + zc_max - 1) / zc_max));
+  }
   const int zc = (op.nz + chunks - 1) / chunks;
   const uint32_t ntiles = xy * uint32_t((op.nz + zc - 1) / zc);
   const dim3 grid(round_grid(ntiles), sl.count);
   const T* sv = reinterpret_cast<const T*>(h.s);
-  if constexpr (sizeof(T) < 8) {
-    // buffer-addressed form: plane byte offsets must fit the 32-bit range
-    if (int64_t(op.nx) * op.ny * int64_t(sizeof(T)) <= 0x7FFFFFF0) {
-      k_stencil7_fused_buf<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc,
-                                                             tiles_x, tiles_y, ntiles, guard, h.ldw, sl.first);
-      return;
-    }
-  }
-  // float64 (its rings do not fit the unrolled form in 128 registers) and larger planes
-  k_stencil7_fused<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
-                                                     tiles_y, ntiles, guard, h.ldw, sl.first);
+  // a tile's planes fit one descriptor's range (effective_fuse admits only planes for which zc >= 1 does)
+  if ((int64_t(zc) + 2 * S + 1) * int64_t(op.nx) * op.ny * int64_t(sizeof(T)) > kMaxSpanBytes)
+    fail(PCHEB_INVALID, "fused pass: x-y plane too large for one buffer descriptor");
+  if constexpr (sizeof(T) < 8)
+    k_stencil7_fused_buf<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
+                                                           tiles_y, ntiles, guard, h.ldw, sl.first);
+  else
+    k_stencil7_fused_buf64<S, TY, NT><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
+                                                          tiles_y, ntiles, guard, h.ldw, sl.first);
 }
 
 template <class T>
@@ -95,12 +99,14 @@ static void launch_fused_any(const Handle& h, Slots sl, int S, const T* ya, cons
                              const DevState* guard, hipStream_t s) {
   constexpr int TY = PCHEB_FUSED_TY, NT = PCHEB_FUSED_NT;
   if constexpr (sizeof(T) == 8) {
+    // float64 rings of three or four levels fit 128 registers only with two points per
+    // thread (64 x 16 tiles); two levels take 64 x 32 tiles
     if (S == 2)
       launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
-    else if (S == 4)  // float64 rings of four levels fit 128 registers and 160 KiB of LDS on 64 x 16 tiles
-      launch_fused<T, 4, 16, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+    else if (S == 3)
+      launch_fused<T, 3, 16, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
     else
-      launch_fused<T, 3, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
+      launch_fused<T, 4, 16, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
   } else {
     if (S == 2)
       launch_fused<T, 2, TY, NT>(h, sl, ya, yb, oa, ob, j, guard, s);
@@ -112,10 +118,12 @@ static void launch_fused_any(const Handle& h, Slots sl, int S, const T* ya, cons
 }
 
 // Steps per pass: fusion applies to the 7-point operator with four iterate
-// buffers and x-y planes of fewer than 2^31 points (32-bit in-plane offsets).
+// buffers and x-y planes small enough that a tile's descriptor span of at least
+// one plane plus 2 S + 1 halo planes stays within kMaxSpanBytes.
 static int effective_fuse(const Handle& h) {
+  const int64_t plane_bytes = int64_t(h.op.nx) * h.op.ny * int64_t(h.elem);
   const bool ok = h.op.kind == PCHEB_OP_STENCIL7 && h.fuse >= 2 && h.nY >= 4 &&
-                  int64_t(h.op.nx) * h.op.ny < (int64_t(1) << 31);
+                  plane_bytes * (2 * std::min(h.fuse, 4) + 2) <= kMaxSpanBytes;
   return ok ? h.fuse : 1;
 }
 
