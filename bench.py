@@ -447,6 +447,14 @@ def run_c3(torch, pc, W, dev):
     pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
     lo, hi = pc.pcheb_estimate_bounds(op, v0, 30)
     hi *= 1.01
+    # the operator's condition number: DACG's lambda_min (an upper estimate, Temple-tight at its
+    # tolerance) and 300 power steps for lambda_max, the paper's estimators (Sec. 5.1)
+    t0 = time.perf_counter()
+    est = pc.pcheb_estimate_bounds_pdacg(op, v0, 300, 1e-3, 200000)
+    est_s = time.perf_counter() - t0
+    log(f"c3: Lanczos(30) [{lo:.6g}, {hi / 1.01:.6g}]; power(300) lambda_max {est['lambda_max']:.6g}, DACG(1e-3) "
+        f"lambda_min {est['lambda_min']:.6g} in {est['dacg_steps']} steps ({est_s:.2f} s): "
+        f"kappa ~ {est['lambda_max'] / est['lambda_min']:.4g}")
     del v0
     rows = []
     with pc.pcheb_setup(op, 0, lo, hi) as h0:
@@ -473,7 +481,10 @@ def run_c3(torch, pc, W, dev):
             log(f"  c3 k={k} {prec}: {row}")
     print(json.dumps({"config": "c3", "workload": "27-point harmonic diffusion 192^3, lognormal(0,2) cells seed 1, "
                       "Lanczos(30) bounds x1.01, b = A x*, tol 1e-8", "lambda_min": lo, "lambda_max": hi,
-                      "kappa_estimate": hi / lo, "rows": rows}), flush=True)
+                      "kappa_estimate_lanczos": hi / lo, "dacg_lambda_min": est["lambda_min"],
+                      "dacg_steps": est["dacg_steps"], "dacg_relres": est["dacg_relres"],
+                      "power300_lambda_max": est["lambda_max"],
+                      "kappa_dacg": est["lambda_max"] / est["lambda_min"], "rows": rows}), flush=True)
 
 
 def run_c4(torch, pc, W, dev):

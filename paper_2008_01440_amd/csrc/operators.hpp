@@ -525,16 +525,24 @@ struct SlotSet {
   In in[kMultiSlots];
   Epi epi[kMultiSlots];
   bool on[kMultiSlots];
-  // true if no slot of the block is active
+  // true if no slot of the block is active.  An inactive slot's input is pointed at
+  // an active slot's vector, so the inner loops read for every slot without a
+  // branch (a branch per slot there keeps each slot's gathers from overlapping the
+  // next one's); its sums are computed and dropped.
   __device__ __forceinline__ bool bind(const In& in0, const Epi& epi0, int first, int last) {
     bool any = false;
+    In active = in0;
 #pragma unroll
-    for (int k = 0; k < kMultiSlots; ++k) {
+    for (int k = kMultiSlots - 1; k >= 0; --k) {
       in[k] = in0;
       epi[k] = epi0;
       on[k] = first + k < last && !bind_slot(in[k], epi[k], first + k);
+      if (on[k]) active = in[k];
       any = any || on[k];
     }
+#pragma unroll
+    for (int k = 0; k < kMultiSlots; ++k)
+      if (!on[k]) in[k] = active;
     return !any;
   }
 };
@@ -598,13 +606,11 @@ __global__ __launch_bounds__(kBlock) void k_csr_multi(const int32_t* __restrict_
         const int32_t x0 = col[c0], x1 = col[c1];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
+          const acc v0 = a0 * ss.in[k].ld(x0);
+          const acc v1 = a1 * ss.in[k].ld(x1);
           acc sum = acc(0);
-          if (ss.on[k]) {
-            const acc v0 = a0 * ss.in[k].ld(x0);
-            const acc v1 = a1 * ss.in[k].ld(x1);
-            sum += ok0 ? v0 : acc(0);
-            sum += ok1 ? v1 : acc(0);
-          }
+          sum += ok0 ? v0 : acc(0);
+          sum += ok1 ? v1 : acc(0);
           sums[it][k] = sum;
         }
       }
@@ -614,8 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_multi(const int32_t* __restrict_
           const acc a = acc(Store<Tv>::ld(val, j));
           const int32_t x = col[j];
 #pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if (ss.on[k]) sums[it][k] += a * ss.in[k].ld(x);
+          for (int k = 0; k < NS; ++k) sums[it][k] += a * ss.in[k].ld(x);
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -637,8 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_multi(const int32_t* __restrict_
           const acc a = acc(Store<Tv>::ld(val, j));
           const int32_t x = col[j];
 #pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if (ss.on[k]) sums[k] += a * ss.in[k].ld(x);
+          for (int k = 0; k < NS; ++k) sums[k] += a * ss.in[k].ld(x);
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -703,8 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_multi(const int64_t* __restrict
       const acc a = acc(Store<Tv>::ld(val, e));
       const int32_t x = col[e];
 #pragma unroll
-      for (int k = 0; k < NS; ++k)
-        if (ss.on[k]) sum[k] += a * ss.in[k].ld(x);
+      for (int k = 0; k < NS; ++k) sum[k] += a * ss.in[k].ld(x);
     }
 #pragma unroll
     for (int k = 0; k < NS; ++k)
