@@ -53,6 +53,12 @@ MUTANTS = [
      "one-sided (nonsymmetric) scaling"),
     ("nc_pcg", "x_hat = dm * res.x", "x_hat = res.x / dm", "solution mapped back with D^1/2"),
     ("nc_pcg", "b = dm * b_hat", "b = b_hat / dm", "right-hand side scaled with D^1/2"),
+    ("nc_apply_unscaled", "return dm * chebyshev_apply(lambda v: a @ v, dm * r_hat, c, k)",
+     "return chebyshev_apply(lambda v: a @ v, dm * r_hat, c, k)", "unscaled apply without the outer D^-1/2"),
+    ("nc_apply_unscaled", "chebyshev_apply(lambda v: a @ v, dm * r_hat, c, k)",
+     "chebyshev_apply(lambda v: a @ v, r_hat / dm, c, k)", "unscaled apply input scaled with D^1/2"),
+    ("nc_apply_unscaled", "c = chebyshev_scalars(lambda_min, lambda_max, k, s)",
+     "c = chebyshev_scalars(lambda_min, lambda_max, k, 1.0)", "unscaled apply ignores the modified parameter"),
     # spectra and estimators
     ("preconditioned_spectrum", "return eigs * p", "return p", "spectrum of p_k(A) instead of p_k(A) A"),
     ("cluster_indicator", "mu / mu.min() < 1.1", "mu / mu.min() < 1.01", "cluster threshold"),
