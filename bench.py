@@ -14,9 +14,9 @@ and bfloat16 recurrences inside the float64 PCG) and the CSR operator; reports
 the dominant kernel (the fused pass of four middle Chebyshev steps) against
 the HBM roofline with HIP events from separate kernel-timed solves; runs a
 short serving leg (200 requests of the mixed 7-/27-point trace at 50 req/s);
-and solves the same problem once with the FP64 CPU oracle, which gives both
-the CPU baseline and the iteration and solution differences of every GPU
-variant against the oracle.
+and solves the same problem once with the FP64 CPU oracle (the C/OpenMP one,
+on all host threads and on one), which gives both the CPU baseline and the
+iteration and solution differences of every GPU variant against the oracle.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 50] [--prec f64] [--fuse 4] [--sweep]
 """
@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--sweep-kinds", default="stencil7,csr,sell", help="operators of the sweep")
     ap.add_argument("--sweep-degrees", default="0,5,10,20,30,50,100", help="degrees of the sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-oracle", default="omp", choices=["omp", "numpy"],
+                    help="oracle of the CPU baseline and the parity check: C/OpenMP (all host threads and one) "
+                         "or numpy/scipy (one thread)")
     ap.add_argument("--no-variants", action="store_true", help="time the flagship only")
     ap.add_argument("--no-serve", action="store_true", help="skip the short serving leg")
     ap.add_argument("--bench-serve-requests", type=int, default=200,
@@ -324,7 +327,7 @@ def main():
 
     cpu, parity = None, None
     if not args.no_cpu:
-        cpu, ref_x, ref_iters = cpu_baseline(rp, ci, v, b, lo, hi, args.k)
+        cpu, ref_x, ref_iters = cpu_baseline(rp, ci, v, b, lo, hi, args.k, args.cpu_oracle)
         parity = {"oracle_iters": ref_iters, "bar": "iterations within +-2, relative solution difference <= 1e-6"}
         for name, r in [("headline", flag)] + list(variants.items()):
             if "x" not in r or r["k"] != args.k:
@@ -859,35 +862,57 @@ def hbm_triad_ceiling(torch, dev, nbytes=1 << 30, reps=20):
     return gbs
 
 
-def cpu_baseline(rp, ci, v, b, lo, hi, k):
-    """The FP64 oracle solving the headline's problem once, completely: the same operator
-    (CSR of the 7-point matrix), right-hand side, bounds, degree, s = 1.001, flexible beta
-    and tol 1e-8, on one thread (scipy's CSR product is single-threaded; numpy's BLAS is
-    held to one thread too).  Returns (the cpu_baseline object, the oracle's solution,
-    its iteration count)."""
-    import oracle
-    from threadpoolctl import threadpool_limits
+def cpu_baseline(rp, ci, v, b, lo, hi, k, which="omp"):
+    """The FP64 oracle solving the headline's problem once, completely (the same operator as a CSR
+    matrix, right-hand side, bounds, degree, s = 1.001, flexible beta, tol 1e-8).  By default the
+    C/OpenMP oracle (oracle/nc_omp.c), on all the host threads this process may use and on one;
+    with which="numpy" the numpy/scipy oracle on one thread (its CSR product is single-threaded).
+    Returns (the cpu_baseline object, the oracle's solution from the first run, its iterations)."""
+    if which == "numpy":
+        import oracle
+        from threadpoolctl import threadpool_limits
 
-    t_last = [time.perf_counter()]
+        t_last = [time.perf_counter()]
 
-    def progress(it, relres):
-        now = time.perf_counter()
-        log(f"  oracle iteration {it}: relres {relres:.3e} ({now - t_last[0]:.1f}s)")
-        t_last[0] = now
+        def progress(it, relres):
+            now = time.perf_counter()
+            log(f"  oracle iteration {it}: relres {relres:.3e} ({now - t_last[0]:.1f}s)")
+            t_last[0] = now
 
-    log("cpu oracle: one full FP64 solve of the same problem, 1 thread")
-    with threadpool_limits(limits=1):
+        log("cpu oracle (numpy): one full FP64 solve of the same problem, 1 thread")
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            res = oracle.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8, flexible=True, progress=progress)
+            dt = time.perf_counter() - t0
+        log(f"cpu oracle: {res.iters} iterations ({res.n_spmv} operator products) in {dt:.1f}s")
+        cpu = {"value": round(1.0 / dt, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one complete solve, not extrapolated: FP64 numpy/scipy oracle on 1 thread (scipy's CSR "
+                         f"product is single-threaded), same {len(rp) - 1}-unknown problem, k={k}, same bounds, "
+                         f"flexible PCG to tol 1e-8: {res.iters} iterations, {res.n_spmv} operator products, "
+                         f"{dt:.2f} s",
+               "seconds": round(dt, 3), "iters": res.iters, "n_spmv": res.n_spmv, "relres_true": res.relres_true}
+        return cpu, res.x_hat, res.iters
+    from oracle import omp
+
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    runs = []
+    for t in dict.fromkeys((threads, 1)):
+        omp.set_threads(t)
+        log(f"cpu oracle (C/OpenMP): one full FP64 solve of the same problem on {t} thread(s)")
         t0 = time.perf_counter()
-        res = oracle.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8, flexible=True, progress=progress)
+        res = omp.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8, flexible=True)
         dt = time.perf_counter() - t0
-    log(f"cpu oracle: {res.iters} iterations ({res.n_spmv} operator products) in {dt:.1f}s, "
-        f"true relres {res.relres_true:.2e}")
-    cpu = {"value": round(1.0 / dt, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
-           "sample": f"one complete solve, not extrapolated: FP64 numpy/scipy oracle on 1 thread (scipy's CSR "
-                     f"product is single-threaded), same {len(rp) - 1}-unknown problem, k={k}, same bounds, "
-                     f"flexible PCG to tol 1e-8: {res.iters} iterations, {res.n_spmv} operator products, "
-                     f"{dt:.2f} s",
-           "seconds": round(dt, 3), "iters": res.iters, "n_spmv": res.n_spmv, "relres_true": res.relres_true}
+        log(f"cpu oracle: {t} thread(s): {res.iters} iterations ({res.n_spmv} operator products) in {dt:.1f}s, "
+            f"true relres {res.relres_true:.2e}")
+        runs.append((t, res, dt))
+    t, res, dt = runs[0]
+    cpu = {"value": round(1.0 / dt, 6), "unit": "solves/s", "cores": t, "kind": "oracle",
+           "sample": f"one complete solve, not extrapolated: the FP64 C/OpenMP oracle (plain CSR PCG, rows split "
+                     f"over {t} host threads) on the same {len(rp) - 1}-unknown problem, k={k}, same bounds, flexible "
+                     f"PCG to tol 1e-8: {res.iters} iterations, {res.n_spmv} operator products, {dt:.2f} s",
+           "seconds": round(dt, 3), "iters": res.iters, "n_spmv": res.n_spmv, "relres_true": res.relres_true,
+           "by_threads": {str(tt): {"seconds": round(d, 3), "solves_per_s": round(1.0 / d, 6), "iters": r.iters}
+                          for tt, r, d in runs}}
     return cpu, res.x_hat, res.iters
 
 

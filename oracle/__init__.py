@@ -2,6 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg are its only users.  The GPU library never imports it.
+``oracle.nc`` is the numpy/scipy oracle; ``oracle.omp`` binds the C/OpenMP one
+(nc_omp.c), which computes the same PCG with the rows split over host threads.
 """
 
 from .nc import (
