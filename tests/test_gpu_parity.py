@@ -592,3 +592,36 @@ def test_batched_apply_and_matvec(pc):
         r = R[j].cpu().numpy()
         assert rel_inf(Z[j].cpu().numpy(), oracle.nc_apply_unscaled(c.rp, c.ci, c.v, r, c.lo, c.hi, 5, 1.001)) <= 1e-11
         assert rel_inf(Y[j].cpu().numpy(), a @ r) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["csr7", "csr_el", "sell_el", "sell_h27"])
+def test_batched_six_rhs_partial_slot_groups(pc, name, prec):
+    """Six right-hand sides: the matrix-once kernels serve slots in groups of four, so a launch has
+    one full group and one of two; slot 2 is zero (finished before the first iteration) and slot 4
+    starts from a right-hand side a hundred times larger.  Each result equals its single solve bit for
+    bit, and a batched matvec equals single matvecs."""
+    c = case(name)
+    k = 5
+    n = c.n
+    ld = n + (n % 2)
+    rhs = [W.uniform(300 + j, n, -1.0, 1.0) for j in range(6)]
+    rhs[2] = np.zeros(n)
+    rhs[4] = 100.0 * rhs[4]
+    B = torch.zeros((6, ld), dtype=torch.float64, device=DEV)
+    for j, r in enumerate(rhs):
+        B[j, :n] = _t(r)
+    with pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, 1.001, prec) as h:
+        X = torch.full_like(B, float("nan"))
+        stb = pc.pcg_solve(h, B[:, :n], X[:, :n], flexible=True)
+        Y = torch.full_like(B, float("nan"))
+        pc.pcheb_matvec(h, B[:, :n], Y[:, :n])
+        for j in range(6):
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            st = pc.pcg_solve(h, B[j, :n].contiguous(), x, flexible=True)
+            assert torch.equal(X[j, :n], x), (name, prec, j, st["iters"])
+            y = torch.empty(n, dtype=torch.float64, device=DEV)
+            pc.pcheb_matvec(h, B[j, :n].contiguous(), y)
+            assert torch.equal(Y[j, :n], y), (name, prec, j)
+    assert stb["status"] == "OK"
+    assert float(X[2, :n].abs().max()) == 0.0
