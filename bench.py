@@ -306,10 +306,10 @@ def main():
         avg_s = r["step_avg_us"] * 1e-6 * S
         achieved = alg_bytes / avg_s / 1e9
         if S > 1:
-            name = ("k_stencil7_fused" if prec == "f64" else "k_stencil7_fused_buf") + f"<S={S},{prec}>"
+            name = ("KFusedPass64" if prec == "f64" else "KFusedPass") + f"<S={S},{prec}>"
             name += f" ({S} middle steps per launch)"
         else:
-            name = f"k_stencil7<SCALED,EpiChebStep<{prec}>> (middle step)"
+            name = f"KStencil7<SCALED,EpiChebStep<{prec}>> (middle step)"
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(prec, S), "kernel": name,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": round(avg_s * 1e6, 2),

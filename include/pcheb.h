@@ -217,6 +217,56 @@ pcheb_status pcg_solve(pcheb_handle h, const double* b, double* x, int32_t nrhs,
 /* Release everything the handle owns (not the borrowed operator arrays).  NULL is allowed. */
 pcheb_status pcheb_destroy(pcheb_handle h);
 
+/*
+ * Work lists: several problems, each with its own operator and preconditioner,
+ * advanced by one launch per kernel for all of them (the Alg. 2 steps and the
+ * PCG iteration of every problem; grid dimension z selects the problem).  This
+ * is the batched counterpart of pcheb_apply and pcg_solve for many problems of
+ * one shape, e.g. one mesh with many coefficient fields: a launch then covers
+ * count times the tiles of one problem, which fills the chip where a single
+ * small problem cannot, and a PCG iteration costs the launches of one problem.
+ *
+ * The handles must describe problems whose launches coincide: the same
+ * operator kind and shape (stencil grid; CSR/SELL n, row-length class and
+ * chunking), precision, degree k, form and steps per pass.  Their operator
+ * data, spectral bounds (so the recurrence coefficients) and 27-point
+ * coefficient fields may all differ.  pcheb_group_create checks this by
+ * comparing the launches each handle would make and fails with INVALID,
+ * naming the first difference, otherwise.
+ * Each problem's result equals, bit for bit, that of the same call on its
+ * own handle: every block does the work it does in that handle's own launch.
+ * The group borrows the handles (count in [1, 1024], no duplicates); they must
+ * outlive it, and while a group call runs no other call may use them.
+ * Errors: INVALID, OOM, HIP.  *out is set only on OK.
+ */
+typedef struct pcheb_group_s* pcheb_group;
+pcheb_status pcheb_group_create(const pcheb_handle* handles, int32_t count, pcheb_group* out);
+
+/*
+ * z_i = P_k(i) r_i for every problem i of the group (pcheb_apply with nrhs 1
+ * on each handle): r and z are device float64 arrays of `count` vectors with
+ * leading dimension ld (vector i at offset i ld), 16-byte aligned, z not
+ * overlapping r.  Enqueued on `stream` without host synchronisation.
+ * Errors: INVALID, HIP, OOM.
+ */
+pcheb_status pcheb_group_apply(pcheb_group g, const double* r, double* z, int64_t ld, hipStream_t stream);
+
+/*
+ * pcg_solve of every problem i of the group on (b_i, x_i), the vectors at
+ * offset i ld of the device float64 arrays b and x, all with the same tol,
+ * maxit and flags (PCG_FLEXIBLE, PCG_X0_GIVEN, PCG_NO_GRAPH; PCG_TIME_KERNELS
+ * and PCG_REFRESH are INVALID here).  Problems converge independently; the
+ * launches skip the finished ones.  stats (host, may be NULL) receives `count`
+ * entries, one per problem.  `stream` is synchronised on return.
+ * Returns OK if every problem converged, else the status of the first that
+ * did not (NOT_CONVERGED or BREAKDOWN), or INVALID, HIP, OOM.
+ */
+pcheb_status pcg_solve_group(pcheb_group g, const double* b, double* x, int64_t ld, double tol,
+                             int32_t maxit, uint32_t flags, pcg_stats* stats, hipStream_t stream);
+
+/* Release the group's tables and graphs (not its handles).  NULL is allowed. */
+pcheb_status pcheb_group_destroy(pcheb_group g);
+
 /* Description of the last failure on the calling thread ("" if none).  Valid until the next call. */
 const char* pcheb_last_error(void);
 

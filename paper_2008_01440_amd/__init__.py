@@ -15,6 +15,7 @@ from ._abi import (
     PCG_TIME_KERNELS,
     PCG_X0_GIVEN,
     PchebError,
+    Group,
     Handle,
     Operator,
     STATUS,
@@ -23,6 +24,7 @@ from ._abi import (
     library_path,
     load_library,
     pcg_solve,
+    pcg_solve_group,
     pcheb_apply,
     pcheb_destroy,
     pcheb_estimate_bounds,
@@ -30,6 +32,9 @@ from ._abi import (
     pcheb_estimate_bounds_pdacg,
     pcheb_fill_uniform,
     pcheb_footprint_bytes,
+    pcheb_group_apply,
+    pcheb_group_create,
+    pcheb_group_destroy,
     pcheb_last_error,
     pcheb_matvec,
     pcheb_set_allocator,
@@ -43,6 +48,7 @@ __all__ = [
     "PCG_TIME_KERNELS",
     "PCG_X0_GIVEN",
     "PchebError",
+    "Group",
     "Handle",
     "Operator",
     "STATUS",
@@ -51,6 +57,7 @@ __all__ = [
     "library_path",
     "load_library",
     "pcg_solve",
+    "pcg_solve_group",
     "pcheb_apply",
     "pcheb_destroy",
     "pcheb_estimate_bounds",
@@ -58,6 +65,9 @@ __all__ = [
     "pcheb_estimate_bounds_pdacg",
     "pcheb_fill_uniform",
     "pcheb_footprint_bytes",
+    "pcheb_group_apply",
+    "pcheb_group_create",
+    "pcheb_group_destroy",
     "pcheb_last_error",
     "pcheb_matvec",
     "pcheb_set_allocator",

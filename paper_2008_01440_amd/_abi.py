@@ -137,6 +137,10 @@ def load_library():
     lib.pcheb_matvec.argtypes = [vp, vp, vp, i32, i64, vp]
     lib.pcg_solve.argtypes = [vp, vp, vp, i32, i64, f64, i32, u32, ctypes.POINTER(CStats), vp]
     lib.pcheb_destroy.argtypes = [vp]
+    lib.pcheb_group_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.pcheb_group_apply.argtypes = [vp, vp, vp, i64, vp]
+    lib.pcg_solve_group.argtypes = [vp, vp, vp, i64, f64, i32, u32, ctypes.POINTER(CStats), vp]
+    lib.pcheb_group_destroy.argtypes = [vp]
     lib.pcheb_last_error.argtypes = []
     lib.pcheb_last_error.restype = ctypes.c_char_p
     lib.pcheb_footprint_bytes.argtypes = [ctypes.POINTER(COperator), ctypes.POINTER(CParams), i32]
@@ -160,6 +164,7 @@ def load_library():
     lib.pserve_get_stats.argtypes = [vp, ctypes.POINTER(CServeStats)]
     lib.pserve_destroy.argtypes = [vp]
     for name in ("pcheb_setup", "pcheb_apply", "pcheb_matvec", "pcg_solve", "pcheb_destroy",
+                 "pcheb_group_create", "pcheb_group_apply", "pcg_solve_group", "pcheb_group_destroy",
                  "pcheb_set_allocator", "pcheb_estimate_bounds", "pcheb_estimate_bounds_noalloc", "pcheb_estimate_bounds_block", "pcheb_estimate_bounds_pdacg", "pcheb_fill_uniform", "pserve_create", "pserve_submit", "pserve_poll", "pserve_wait",
                  "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -324,6 +329,75 @@ def pcheb_destroy(h: Handle):
     if h.ptr:
         _check(load_library().pcheb_destroy(h.ptr))
         h.ptr = None
+
+
+class Group:
+    """An owned pcheb_group over borrowed handles (release with pcheb_group_destroy or as a
+    context manager; the handles must outlive it)."""
+
+    def __init__(self, ptr, handles):
+        self.ptr = ptr
+        self.handles = tuple(handles)
+
+    @property
+    def n(self):
+        return self.handles[0].n
+
+    def __len__(self):
+        return len(self.handles)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        pcheb_group_destroy(self)
+
+
+def pcheb_group_create(handles) -> Group:
+    handles = list(handles)
+    arr = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
+    out = ctypes.c_void_p()
+    _check(load_library().pcheb_group_create(arr, len(handles), ctypes.byref(out)))
+    return Group(out, handles)
+
+
+def _group_layout(g: Group, a, b):
+    """Leading dimension of the (count, >= n) blocks a and b, one row per problem."""
+    for t in (a, b):
+        if t.dim() != 2 or t.shape[0] != len(g):
+            raise ValueError(f"expected a block of {len(g)} rows, one per problem")
+    count, ld = _same_layout(a, b, g.n)
+    return ld
+
+
+def pcheb_group_apply(g: Group, r, z, stream=None):
+    ld = _group_layout(g, r, z)
+    _check(load_library().pcheb_group_apply(g.ptr, _dptr(r, "float64"), _dptr(z, "float64"), ld, _stream(stream)))
+
+
+def pcg_solve_group(g: Group, b, x, tol: float = 1e-8, maxit: int = 100000, flexible: bool = False,
+                    x0_given: bool = False, graph: bool = True, stream=None, check: bool = True) -> list:
+    """Per-problem statistics as dicts.  With check=True, BREAKDOWN and errors raise;
+    NOT_CONVERGED is reported in the dicts."""
+    flags = (PCG_FLEXIBLE if flexible else 0) | (PCG_X0_GIVEN if x0_given else 0) | (0 if graph else PCG_NO_GRAPH)
+    ld = _group_layout(g, b, x)
+    sts = (CStats * len(g))()
+    status = load_library().pcg_solve_group(g.ptr, _dptr(b, "float64"), _dptr(x, "float64"), ld, tol, maxit, flags,
+                                            sts, _stream(stream))
+    if check:
+        _check(status, allowed=(0, 5))
+    out = []
+    for st in sts:
+        d = {name: getattr(st, name) for name, _ in CStats._fields_ if name != "pad0"}
+        d["status"] = STATUS.get(int(st.status), str(int(st.status)))
+        out.append(d)
+    return out
+
+
+def pcheb_group_destroy(g: Group):
+    if g.ptr:
+        _check(load_library().pcheb_group_destroy(g.ptr))
+        g.ptr = None
 
 
 def pcheb_footprint_bytes(op: Operator, k: int, lambda_min: float = 0.1, lambda_max: float = 2.0,

@@ -577,7 +577,7 @@ struct EigWork {
 static void normalise_start(Handle& h, const EigWork& w, const double* v, hipStream_t s) {
   const int64_t n = h.n;
   k_eg_norm2<<<kLzGrid, kBlock, 0, s>>>(v, n, h.rb());
-  k_finalize<1, FinInvNorm><<<1, kFinThreads, 0, s>>>(FinInvNorm{w.E}, h.rb(), kLzGrid, nullptr, 0);
+  launch<KFinalize<1, FinInvNorm>>(1, kFinThreads, 0, s, FinInvNorm{w.E}, h.rb(), kLzGrid, nullptr, 0);
   double inv = 0.0;
   PCHEB_HIP_CHECK(hipMemcpyAsync(&inv, &w.E->inv, sizeof(double), hipMemcpyDeviceToHost, s));
   PCHEB_HIP_CHECK(hipStreamSynchronize(s));
@@ -618,7 +618,7 @@ static void dacg(Handle& h, const EigWork& w, const double* v0, double tol, int 
   normalise_start(h, w, v0, s);
   launch_ahat(h, InScaled{w.x, w.isd, n}, EpiDacgStart{w.ax, w.isd, w.x, w.E, nullptr, nullptr}, 0, 1, s);
   k_eg_start<<<kLzGrid, kBlock, 0, s>>>(w.x, w.ax, w.g, w.p, w.E, n, h.rb());
-  k_finalize<1, FinDacgStart><<<1, kFinThreads, 0, s>>>(FinDacgStart{w.E}, h.rb(), kLzGrid, nullptr, 0);
+  launch<KFinalize<1, FinDacgStart>>(1, kFinThreads, 0, s, FinDacgStart{w.E}, h.rb(), kLzGrid, nullptr, 0);
   const DevState* guard = &w.E->st;
   EigState e{};
   constexpr int kGroup = 16;  // steps enqueued between reads of the state
@@ -630,7 +630,7 @@ static void dacg(Handle& h, const EigWork& w, const double* v0, double tol, int 
       k_eg_direction<<<kLzGrid, kBlock, 0, s>>>(w.g, w.p, w.E, n);
       launch_ahat(h, InScaled{w.p, w.isd, n}, EpiDacgProduct{w.ap, w.isd, w.p, w.x, w.E, nullptr, guard}, 0, 1, s);
       k_eg_update<<<kLzGrid, kBlock, 0, s>>>(w.x, w.ax, w.p, w.ap, w.g, w.E, n, h.rb());
-      k_finalize<3, FinDacgUpdate><<<1, kFinThreads, 0, s>>>(FinDacgUpdate{w.E}, h.rb(), kLzGrid, guard, 0);
+      launch<KFinalize<3, FinDacgUpdate>>(1, kFinThreads, 0, s, FinDacgUpdate{w.E}, h.rb(), kLzGrid, guard, 0);
     }
     PCHEB_HIP_CHECK(hipGetLastError());
   }

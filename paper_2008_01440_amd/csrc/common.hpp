@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "launch.hpp"
+
 namespace pcheb {
 
 constexpr int kWave = 64;          // CDNA wavefront width
@@ -174,8 +176,13 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], ReduceBuf rb, int
 constexpr int kFinThreads = 1024;
 static_assert(kMaxGrid % kFinThreads == 0, "the finalize loads kMaxGrid / kFinThreads partials per thread");
 template <int NV, class Fin>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(Fin fin, ReduceBuf rb, uint32_t nblocks,
-                                                          const DevState* guard, int slot0) {
+struct KFinalize {
+  static constexpr int kThreads = kFinThreads;
+  __device__ static void run(Fin fin, ReduceBuf rb, uint32_t nblocks, const DevState* guard, int slot0);
+};
+template <int NV, class Fin>
+__device__ __forceinline__ void KFinalize<NV, Fin>::run(Fin fin, ReduceBuf rb, uint32_t nblocks, const DevState* guard,
+                                                        int slot0) {
   const int slot = slot0 + int(blockIdx.x);
   if (guard && guard[slot].done != kRunning) return;
   fin.bind(slot);

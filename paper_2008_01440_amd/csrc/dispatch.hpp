@@ -17,7 +17,7 @@ namespace pcheb {
 #endif
 // CSR: from kCsrWideRows rows on, a wavefront walks min(L, kCsrWidePasses)
 // passes of 64 / L rows (L lanes per row); below, one pass.  Four passes keep
-// eight nonzero slots per lane in flight in the straight-line part of k_csr
+// eight nonzero slots per lane in flight in the straight-line part of KCsr
 // (elasticity, L = 32: 32 passes 1270 us, 8 passes 1095 us, 4 passes 988 us,
 // 2 passes 1030 us per F32 step).
 constexpr int64_t kCsrWideRows = int64_t(1) << 20;
@@ -43,7 +43,7 @@ inline StencilGrid stencil_grid(const pcheb_operator& op, int rows, int zc) {
 // Tv: value type of CSR/SELL arrays (float64 for A_hat; storage type for D^-1 A_hat).
 // The launch covers solve slots slot0 .. slot0 + nslots - 1: one slot per grid row
 // (dimension y) for the stencils; CSR and SELL launches of several slots read the
-// matrix once for every kMultiSlots of them (k_csr_multi, k_sell_multi).
+// matrix once for every kMultiSlots of them (KCsrMulti, KSellMulti).
 template <bool SCALED, class Tv, class In, class Epi>
 void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Epi epi, int slot0, int nslots,
                hipStream_t s) {
@@ -54,8 +54,8 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
     case PCHEB_OP_STENCIL7: {
       const StencilGrid g = stencil_grid(op, kSt7Rows, kSt7ZChunk);
       grid = g.grid;
-      k_stencil7<SCALED, kSt7Rows, kSt7ZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, kSt7Rows), 0, s>>>(
-          in, epi, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
+      launch<KStencil7<SCALED, kSt7Rows, kSt7ZChunk, In, Epi>>(dim3(grid, nslots), dim3(64, kSt7Rows), 0, s, in, epi,
+          op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_STENCIL27H: {
@@ -63,35 +63,35 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       grid = g.grid;
       const acc* rho = sizeof(acc) == 8 ? reinterpret_cast<const acc*>(h.rho64) : reinterpret_cast<const acc*>(h.rho_lo);
       const acc* invd = sizeof(acc) == 8 ? reinterpret_cast<const acc*>(h.invd) : reinterpret_cast<const acc*>(h.invd_lo);
-      k_stencil27h_lds<SCALED, kSt7Rows, kSt7ZChunk, In, Epi><<<dim3(grid, nslots), dim3(64, kSt7Rows), 0, s>>>(
-          in, epi, rho, invd, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
+      launch<KStencil27h<SCALED, kSt7Rows, kSt7ZChunk, In, Epi>>(dim3(grid, nslots), dim3(64, kSt7Rows), 0, s, in, epi,
+          rho, invd, op.nx, op.ny, op.nz, g.tiles_x, g.tiles_y, g.ntiles, h.rb(), slot0);
       break;
     }
     case PCHEB_OP_CSR: {
       // min(L, kCsrWidePasses) passes per wavefront for large matrices, one for small ones
       const bool wide = h.n >= kCsrWideRows;
-#define PCHEB_CSR_CASE(L)                                                                                  \
-  case L: {                                                                                                \
-    constexpr int PW = L < kCsrWidePasses ? L : kCsrWidePasses;                                            \
-    const int64_t rows = int64_t(kBlock / kWave) * (wide ? PW * (kWave / L) : kWave / L);                  \
-    const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);                                              \
-    grid = round_grid(tiles);                                                                              \
-    if (nslots > 1) {                                                                                      \
-      const dim3 mg(grid, (nslots + kMultiSlots - 1) / kMultiSlots);                                       \
-      if (wide)                                                                                            \
-        k_csr_multi<L, PW, Tv, In, Epi><<<mg, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n,  \
-                                                             uint32_t(tiles), h.rb(), slot0, nslots);      \
-      else                                                                                                 \
-        k_csr_multi<L, 1, Tv, In, Epi><<<mg, kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi, h.n,   \
-                                                            uint32_t(tiles), h.rb(), slot0, nslots);       \
-    } else if (wide) {                                                                                     \
-      k_csr<L, PW, Tv, In, Epi><<<dim3(grid, 1), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi,    \
-                                                                h.n, uint32_t(tiles), h.rb(), slot0);      \
-    } else {                                                                                               \
-      k_csr<L, 1, Tv, In, Epi><<<dim3(grid, 1), kBlock, 0, s>>>(op.rowptr, op.colind, csr_val, in, epi,     \
-                                                               h.n, uint32_t(tiles), h.rb(), slot0);       \
-    }                                                                                                      \
-    break;                                                                                                 \
+#define PCHEB_CSR_CASE(L)                                                                                        \
+  case L: {                                                                                                      \
+    constexpr int PW = L < kCsrWidePasses ? L : kCsrWidePasses;                                                  \
+    const int64_t rows = int64_t(kBlock / kWave) * (wide ? PW * (kWave / L) : kWave / L);                        \
+    const uint64_t tiles = uint64_t((h.n + rows - 1) / rows);                                                    \
+    grid = round_grid(tiles);                                                                                    \
+    if (nslots > 1) {                                                                                            \
+      const dim3 mg(grid, (nslots + kMultiSlots - 1) / kMultiSlots);                                             \
+      if (wide)                                                                                                  \
+        launch<KCsrMulti<L, PW, Tv, In, Epi>>(mg, kBlock, 0, s, op.rowptr, op.colind, csr_val, in, epi, h.n,     \
+            uint32_t(tiles), h.rb(), slot0, nslots);                                                             \
+      else                                                                                                       \
+        launch<KCsrMulti<L, 1, Tv, In, Epi>>(mg, kBlock, 0, s, op.rowptr, op.colind, csr_val, in, epi, h.n,      \
+            uint32_t(tiles), h.rb(), slot0, nslots);                                                             \
+    } else if (wide) {                                                                                           \
+      launch<KCsr<L, PW, Tv, In, Epi>>(dim3(grid, 1), kBlock, 0, s, op.rowptr, op.colind, csr_val, in, epi, h.n, \
+          uint32_t(tiles), h.rb(), slot0);                                                                       \
+    } else {                                                                                                     \
+      launch<KCsr<L, 1, Tv, In, Epi>>(dim3(grid, 1), kBlock, 0, s, op.rowptr, op.colind, csr_val, in, epi, h.n,  \
+          uint32_t(tiles), h.rb(), slot0);                                                                       \
+    }                                                                                                            \
+    break;                                                                                                       \
   }
       switch (h.lanes) {
         PCHEB_CSR_CASE(4)
@@ -108,20 +108,19 @@ void launch_op(const Handle& h, const Tv* csr_val, const Tv* sell_val, In in, Ep
       const uint64_t tiles = uint64_t((h.nchunks + 3) / 4);
       grid = round_grid(tiles);
       if (nslots > 1)
-        k_sell_multi<Tv, In, Epi><<<dim3(grid, (nslots + kMultiSlots - 1) / kMultiSlots), kBlock, 0, s>>>(
-            h.sell_ptr, h.sell_len, h.sell_col, sell_val, h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(), slot0,
-            nslots);
+        launch<KSellMulti<Tv, In, Epi>>(dim3(grid, (nslots + kMultiSlots - 1) / kMultiSlots), kBlock, 0, s, h.sell_ptr,
+            h.sell_len, h.sell_col, sell_val, h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(), slot0, nslots);
       else
-        k_sell<Tv, In, Epi><<<dim3(grid, 1), kBlock, 0, s>>>(h.sell_ptr, h.sell_len, h.sell_col, sell_val,
-                                                             h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(),
-                                                             slot0);
+        launch<KSell<Tv, In, Epi>>(dim3(grid, 1), kBlock, 0, s, h.sell_ptr, h.sell_len, h.sell_col, sell_val,
+            h.sell_perm, in, epi, h.n, uint32_t(tiles), h.rb(), slot0);
       break;
     }
     default:
       fail(PCHEB_INVALID, "unknown operator kind");
   }
   if constexpr (Epi::reduce) {
-    k_finalize<Epi::NV, EpiFin<Epi>><<<nslots, kFinThreads, 0, s>>>(EpiFin<Epi>{epi}, h.rb(), grid, epi.guard, slot0);
+    launch<KFinalize<Epi::NV, EpiFin<Epi>>>(nslots, kFinThreads, 0, s, EpiFin<Epi>{epi}, h.rb(), grid, epi.guard,
+        slot0);
   }
 }
 

@@ -87,11 +87,11 @@ static void launch_fused(const Handle& h, Slots sl, const T* ya, const T* yb, T*
   if ((int64_t(zc) + 2 * S + 1) * int64_t(op.nx) * op.ny * int64_t(sizeof(T)) > kMaxSpanBytes)
     fail(PCHEB_INVALID, "fused pass: x-y plane too large for one buffer descriptor");
   if constexpr (sizeof(T) < 8)
-    k_stencil7_fused_buf<S, TY, NT, T><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
-                                                           tiles_y, ntiles, guard, h.ldw, sl.first);
+    launch<KFusedPass<S, TY, NT, T>>(grid, NT, 0, s, ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x, tiles_y,
+        ntiles, guard, h.ldw, sl.first);
   else
-    k_stencil7_fused_buf64<S, TY, NT><<<grid, NT, 0, s>>>(ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x,
-                                                          tiles_y, ntiles, guard, h.ldw, sl.first);
+    launch<KFusedPass64<S, TY, NT>>(grid, NT, 0, s, ya, yb, sv, oa, ob, cf, op.nx, op.ny, op.nz, zc, tiles_x, tiles_y,
+        ntiles, guard, h.ldw, sl.first);
 }
 
 template <class T>

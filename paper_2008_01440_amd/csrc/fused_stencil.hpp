@@ -27,8 +27,8 @@
 // l >= 2 is y_{j+l-2}; levels 1..S have registers and LDS planes, level S+1
 // goes straight to memory.
 //
-// Both kernels (k_stencil7_fused_buf for float32 and bfloat16 storage,
-// k_stencil7_fused_buf64 for float64) keep the inner loop to the recurrence
+// Both kernels (KFusedPass for float32 and bfloat16 storage,
+// KFusedPass64 for float64) keep the inner loop to the recurrence
 // arithmetic:
 //  * memory accesses are buffer instructions: each vector gets one descriptor
 //    per tile, covering the planes the tile touches, and a plane is selected
@@ -102,12 +102,20 @@ struct BufIo<bf16> {
 constexpr int64_t kMaxSpanBytes = kOutOfRange;
 
 template <int S, int TY, int NT, class T>
-__global__ __launch_bounds__(NT) void k_stencil7_fused_buf(const T* __restrict__ ya, const T* __restrict__ yb,
-                                                           const T* __restrict__ sv, T* __restrict__ out_a,
-                                                           T* __restrict__ out_b, FusedCoef<float, S> cf, int nx,
-                                                           int ny, int nz, int zc, uint32_t tiles_x,
-                                                           uint32_t tiles_y, uint32_t ntiles, const DevState* guard,
-                                                           int64_t ld, int slot0) {
+struct KFusedPass {
+  static constexpr int kThreads = NT;
+  __device__ static void run(const T* __restrict__ ya, const T* __restrict__ yb, const T* __restrict__ sv,
+                             T* __restrict__ out_a, T* __restrict__ out_b, FusedCoef<float, S> cf, int nx, int ny,
+                             int nz, int zc, uint32_t tiles_x, uint32_t tiles_y, uint32_t ntiles, const DevState* guard,
+                             int64_t ld, int slot0);
+};
+template <int S, int TY, int NT, class T>
+__device__ __forceinline__ void KFusedPass<S, TY, NT, T>::run(const T* __restrict__ ya, const T* __restrict__ yb,
+                                                              const T* __restrict__ sv, T* __restrict__ out_a,
+                                                              T* __restrict__ out_b, FusedCoef<float, S> cf, int nx,
+                                                              int ny, int nz, int zc, uint32_t tiles_x,
+                                                              uint32_t tiles_y, uint32_t ntiles, const DevState* guard,
+                                                              int64_t ld, int slot0) {
   constexpr int TX = 64;
   constexpr int RX = TX + 2 * S;
   constexpr int RY = TY + 2 * S;
@@ -293,17 +301,24 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused_buf(const T* __restrict__
   }
 }
 
-// k_stencil7_fused_buf64: the float64 pass in the buffer-addressed form of
-// k_stencil7_fused_buf (per-tile descriptors, out-of-range offsets instead of
+// KFusedPass64: the float64 pass in the buffer-addressed form of
+// KFusedPass (per-tile descriptors, out-of-range offsets instead of
 // masks), with the levels' in-plane neighbours in planar LDS buffers, two per
 // level (level l writes buffer adv & 1, level l + 1 reads the other one a step
 // later; a record of three planes per level, as the float32 pass keeps, does not
 // fit 160 KiB in float64).  The z loop is unrolled by six, so both the LDS parity
 // and the register ring's phase are compile-time constants and every LDS access
-// is an immediate offset from one base per owned point.  Same values in the same
-// order as k_stencil7_fused.
+// is an immediate offset from one base per owned point.
 template <int S, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_stencil7_fused_buf64(const double* __restrict__ ya,
+struct KFusedPass64 {
+  static constexpr int kThreads = NT;
+  __device__ static void run(const double* __restrict__ ya, const double* __restrict__ yb,
+                             const double* __restrict__ sv, double* __restrict__ out_a, double* __restrict__ out_b,
+                             FusedCoef<double, S> cf, int nx, int ny, int nz, int zc, uint32_t tiles_x,
+                             uint32_t tiles_y, uint32_t ntiles, const DevState* guard, int64_t ld, int slot0);
+};
+template <int S, int TY, int NT>
+__device__ __forceinline__ void KFusedPass64<S, TY, NT>::run(const double* __restrict__ ya,
                                                              const double* __restrict__ yb,
                                                              const double* __restrict__ sv, double* __restrict__ out_a,
                                                              double* __restrict__ out_b, FusedCoef<double, S> cf,
@@ -345,7 +360,7 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused_buf64(const double* __res
     const int z1 = z0 + zc < nz ? z0 + zc : nz;
     const int zs = z0 - S;
     const int nadv = (z1 - z0) + 2 * S;
-    // descriptors as in k_stencil7_fused_buf
+    // descriptors as in KFusedPass
     const int zlo = zs - 1 > 0 ? zs - 1 : 0;
     const int zhi = zs + nadv - 1 < nz - 1 ? zs + nadv - 1 : nz - 1;
     const int span = (zhi - zlo + 1) * plane_bytes;
@@ -356,7 +371,7 @@ __global__ __launch_bounds__(NT) void k_stencil7_fused_buf64(const double* __res
     const auto r_oa = tile_rsrc(out_a), r_ob = tile_rsrc(out_b);
     auto plane_soff = [&](int zz) { return zz >= 0 && zz < nz ? (zz - zlo) * plane_bytes : 0; };
 
-    // owned points p = tid + NT m (as in k_stencil7_fused_buf): dom[m] in the grid,
+    // owned points p = tid + NT m (as in KFusedPass): dom[m] in the grid,
     // ldo[m] / sto[m] byte offsets of loads and output stores (out of range where
     // there is nothing to do), q[m] the LDS index (the tail margin for absent points)
     int q[P], ldo[P], sto[P];

@@ -76,8 +76,15 @@ __device__ __forceinline__ bool bind_slot(In& in, Epi& epi, int slot) {
 // outside the grid are zero.  Every thread of a block takes part in every
 // barrier; points outside the grid skip only the epilogue.
 template <bool SCALED, int TY, int ZC, class In, class Epi>
-__global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, int ny, int nz, uint32_t tiles_x,
-                                                      uint32_t tiles_y, uint32_t ntiles, ReduceBuf rb, int slot0) {
+struct KStencil7 {
+  static constexpr int kThreads = 64 * TY;
+  __device__ static void run(In in, Epi epi, int nx, int ny, int nz, uint32_t tiles_x, uint32_t tiles_y,
+                             uint32_t ntiles, ReduceBuf rb, int slot0);
+};
+template <bool SCALED, int TY, int ZC, class In, class Epi>
+__device__ __forceinline__ void KStencil7<SCALED, TY, ZC, In, Epi>::run(In in, Epi epi, int nx, int ny, int nz,
+                                                                        uint32_t tiles_x, uint32_t tiles_y,
+                                                                        uint32_t ntiles, ReduceBuf rb, int slot0) {
   static_assert(TY >= 2 && 2 * TY <= 64, "halo loads need two waves and at most 64 halo columns");
   using acc = typename Epi::acc;
   constexpr int W = 64 + 2;  // LDS row: the tile row and its two halo columns
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, in
 
 // ------------------------------------------------------------------ 27-point harmonic stencil
 //
-// Tiles and planes as in k_stencil7: a block of 64 x TY threads owns 64 x TY
+// Tiles and planes as in KStencil7: a block of 64 x TY threads owns 64 x TY
 // columns, marches ZC planes, and stages each incoming plane of y and of
 // rho = 1 / (2 kappa) with its one-point halo (corners included) in LDS, two
 // buffers and one barrier per plane.  Each thread copies its 3 x 3
@@ -180,11 +187,19 @@ __global__ __launch_bounds__(64 * TY) void k_stencil7(In in, Epi epi, int nx, in
 //   else:    m = y_i / invd_i - sum_n w_in y_n      (A_hat y, double only).
 // The neighbour sum runs over dz, dy, dx in order.
 template <bool SCALED, int TY, int ZC, class In, class Epi>
-__global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
-                                                            const typename Epi::acc* __restrict__ rho,
-                                                            const typename Epi::acc* __restrict__ invd, int nx,
-                                                            int ny, int nz, uint32_t tiles_x, uint32_t tiles_y,
-                                                            uint32_t ntiles, ReduceBuf rb, int slot0) {
+struct KStencil27h {
+  static constexpr int kThreads = 64 * TY;
+  __device__ static void run(In in, Epi epi, const typename Epi::acc* __restrict__ rho,
+                             const typename Epi::acc* __restrict__ invd, int nx, int ny, int nz, uint32_t tiles_x,
+                             uint32_t tiles_y, uint32_t ntiles, ReduceBuf rb, int slot0);
+};
+template <bool SCALED, int TY, int ZC, class In, class Epi>
+__device__ __forceinline__ void KStencil27h<SCALED, TY, ZC, In, Epi>::run(In in, Epi epi,
+                                                                          const typename Epi::acc* __restrict__ rho,
+                                                                          const typename Epi::acc* __restrict__ invd,
+                                                                          int nx, int ny, int nz, uint32_t tiles_x,
+                                                                          uint32_t tiles_y, uint32_t ntiles,
+                                                                          ReduceBuf rb, int slot0) {
   static_assert(TY >= 2 && 2 * (TY + 2) <= 64, "halo loads need two waves and at most 64 side points");
   using acc = typename Epi::acc;
   static_assert(SCALED || sizeof(acc) == 8, "A_hat products run in double");
@@ -207,7 +222,7 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
   const int tx = int(threadIdx.x), ty = int(threadIdx.y);
   const acc kOut = acc(1);  // rho of a cell outside the grid (its y is 0)
   auto ldy = [&](bool ok, int64_t j) {
-    if constexpr (In::narrow) {  // as in k_stencil7: no branch around narrow loads
+    if constexpr (In::narrow) {  // as in KStencil7: no branch around narrow loads
       const acc v = acc(in.ld(ok ? j : 0));
       return ok ? v : acc(0);
     } else {
@@ -380,9 +395,18 @@ __global__ __launch_bounds__(64 * TY) void k_stencil27h_lds(In in, Epi epi,
 // loads are in flight together (7-point F32 step 347 -> 311 us on 256^3);
 // longer rows finish in a loop.  A tile is the rows of one block.
 template <int LANES, int PASSES, class Tv, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                const Tv* __restrict__ val, In in, Epi epi, int64_t n,
-                                                uint32_t ntiles, ReduceBuf rb, int slot0) {
+struct KCsr {
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                             const Tv* __restrict__ val, In in, Epi epi, int64_t n, uint32_t ntiles, ReduceBuf rb,
+                             int slot0);
+};
+template <int LANES, int PASSES, class Tv, class In, class Epi>
+__device__ __forceinline__ void KCsr<LANES, PASSES, Tv, In, Epi>::run(const int32_t* __restrict__ rowptr,
+                                                                      const int32_t* __restrict__ col,
+                                                                      const Tv* __restrict__ val, In in, Epi epi,
+                                                                      int64_t n, uint32_t ntiles, ReduceBuf rb,
+                                                                      int slot0) {
   using acc = typename Epi::acc;
   const int slot = slot0 + int(blockIdx.y);
   if (bind_slot(in, epi, slot)) return;
@@ -469,11 +493,19 @@ __global__ __launch_bounds__(kBlock) void k_csr(const int32_t* __restrict__ rowp
 // one 64-wide unit-stride access.  Padding slots hold column 0 and value 0.
 // perm (may be null = identity) maps a sorted position to its original row.
 template <class Tv, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chunk_ptr,
-                                                 const int32_t* __restrict__ chunk_len,
-                                                 const int32_t* __restrict__ col, const Tv* __restrict__ val,
-                                                 const int32_t* __restrict__ perm, In in, Epi epi, int64_t n,
-                                                 uint32_t ntiles, ReduceBuf rb, int slot0) {
+struct KSell {
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const int64_t* __restrict__ chunk_ptr, const int32_t* __restrict__ chunk_len,
+                             const int32_t* __restrict__ col, const Tv* __restrict__ val,
+                             const int32_t* __restrict__ perm, In in, Epi epi, int64_t n, uint32_t ntiles, ReduceBuf rb,
+                             int slot0);
+};
+template <class Tv, class In, class Epi>
+__device__ __forceinline__ void KSell<Tv, In, Epi>::run(const int64_t* __restrict__ chunk_ptr,
+                                                        const int32_t* __restrict__ chunk_len,
+                                                        const int32_t* __restrict__ col, const Tv* __restrict__ val,
+                                                        const int32_t* __restrict__ perm, In in, Epi epi, int64_t n,
+                                                        uint32_t ntiles, ReduceBuf rb, int slot0) {
   using acc = typename Epi::acc;
   const int slot = slot0 + int(blockIdx.y);
   if (bind_slot(in, epi, slot)) return;
@@ -510,13 +542,13 @@ __global__ __launch_bounds__(kBlock) void k_sell(const int64_t* __restrict__ chu
 
 // ------------------------------------------------------------------ several right-hand sides, matrix read once
 //
-// k_csr_multi and k_sell_multi: a block serves kMultiSlots consecutive solve
+// KCsrMulti and KSellMulti: a block serves kMultiSlots consecutive solve
 // slots (slot0 + blockIdx.y * kMultiSlots + k, k < kMultiSlots, up to slot0 +
 // nslots), reads every column index and value of its rows once and applies it
 // to each active slot's vector.  Tiles, rows, lanes and the order of every
 // slot's sums are those of the single-slot kernels, and a slot's block
 // partials go to the same places, so each slot's results are bitwise those of
-// k_csr / k_sell alone; only the matrix traffic is shared.  Slots whose solve
+// KCsr / KSell alone; only the matrix traffic is shared.  Slots whose solve
 // has finished are skipped.
 constexpr int kMultiSlots = 4;
 
@@ -548,10 +580,18 @@ struct SlotSet {
 };
 
 template <int LANES, int PASSES, class Tv, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_csr_multi(const int32_t* __restrict__ rowptr,
-                                                      const int32_t* __restrict__ col, const Tv* __restrict__ val,
-                                                      In in, Epi epi, int64_t n, uint32_t ntiles, ReduceBuf rb,
-                                                      int slot0, int nslots) {
+struct KCsrMulti {
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                             const Tv* __restrict__ val, In in, Epi epi, int64_t n, uint32_t ntiles, ReduceBuf rb,
+                             int slot0, int nslots);
+};
+template <int LANES, int PASSES, class Tv, class In, class Epi>
+__device__ __forceinline__ void KCsrMulti<LANES, PASSES, Tv, In, Epi>::run(const int32_t* __restrict__ rowptr,
+                                                                           const int32_t* __restrict__ col,
+                                                                           const Tv* __restrict__ val, In in, Epi epi,
+                                                                           int64_t n, uint32_t ntiles, ReduceBuf rb,
+                                                                           int slot0, int nslots) {
   using acc = typename Epi::acc;
   constexpr int NS = kMultiSlots;
   const int first = slot0 + int(blockIdx.y) * NS;
@@ -664,11 +704,21 @@ __global__ __launch_bounds__(kBlock) void k_csr_multi(const int32_t* __restrict_
 }
 
 template <class Tv, class In, class Epi>
-__global__ __launch_bounds__(kBlock) void k_sell_multi(const int64_t* __restrict__ chunk_ptr,
-                                                       const int32_t* __restrict__ chunk_len,
-                                                       const int32_t* __restrict__ col, const Tv* __restrict__ val,
-                                                       const int32_t* __restrict__ perm, In in, Epi epi, int64_t n,
-                                                       uint32_t ntiles, ReduceBuf rb, int slot0, int nslots) {
+struct KSellMulti {
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const int64_t* __restrict__ chunk_ptr, const int32_t* __restrict__ chunk_len,
+                             const int32_t* __restrict__ col, const Tv* __restrict__ val,
+                             const int32_t* __restrict__ perm, In in, Epi epi, int64_t n, uint32_t ntiles, ReduceBuf rb,
+                             int slot0, int nslots);
+};
+template <class Tv, class In, class Epi>
+__device__ __forceinline__ void KSellMulti<Tv, In, Epi>::run(const int64_t* __restrict__ chunk_ptr,
+                                                             const int32_t* __restrict__ chunk_len,
+                                                             const int32_t* __restrict__ col,
+                                                             const Tv* __restrict__ val,
+                                                             const int32_t* __restrict__ perm, In in, Epi epi,
+                                                             int64_t n, uint32_t ntiles, ReduceBuf rb, int slot0,
+                                                             int nslots) {
   using acc = typename Epi::acc;
   constexpr int NS = kMultiSlots;
   const int first = slot0 + int(blockIdx.y) * NS;

@@ -403,8 +403,14 @@ struct FinUpdate {
 };
 
 // x0 = 0: x = 0, r = b, p_old = 0 and the norms of b.
-__global__ void k_start_zero(const double* b, int64_t ldb, double* x, int64_t ldx, double* r, double* p_old,
-                             int64_t ldw, InvDiag invd, int64_t n, ReduceBuf rb, int slot0) {
+struct KStartZero {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const double* b, int64_t ldb, double* x, int64_t ldx, double* r, double* p_old,
+                             int64_t ldw, InvDiag invd, int64_t n, ReduceBuf rb, int slot0);
+};
+__device__ __forceinline__ void KStartZero::run(const double* b, int64_t ldb, double* x, int64_t ldx, double* r,
+                                                double* p_old, int64_t ldw, InvDiag invd, int64_t n, ReduceBuf rb,
+                                                int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   b += slot * ldb;
   x += slot * ldx;
@@ -436,8 +442,14 @@ __global__ void k_start_zero(const double* b, int64_t ldb, double* x, int64_t ld
 // (CSR and SELL gathers, the 27-point stencil); the 7-point kernel forms p as
 // it stages each plane.
 template <class Tz>
-__global__ void k_direction(const Tz* z, const double* p_old, double* p, int64_t ldw, int64_t n,
-                            const DevState* st, int slot0) {
+struct KDirection {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const Tz* z, const double* p_old, double* p, int64_t ldw, int64_t n, const DevState* st,
+                             int slot0);
+};
+template <class Tz>
+__device__ __forceinline__ void KDirection<Tz>::run(const Tz* z, const double* p_old, double* p, int64_t ldw, int64_t n,
+                                                    const DevState* st, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   st += slot;
   if (st->done != kRunning) return;
@@ -457,15 +469,25 @@ __global__ void k_direction(const Tz* z, const double* p_old, double* p, int64_t
 }
 
 // p_old = 0 for the slots of a warm start.
-__global__ void k_zero_slots(double* p, int64_t ldw, int64_t n, int slot0) {
+struct KZeroSlots {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(double* p, int64_t ldw, int64_t n, int slot0);
+};
+__device__ __forceinline__ void KZeroSlots::run(double* p, int64_t ldw, int64_t n, int slot0) {
   p += (slot0 + int64_t(blockIdx.y)) * ldw;
   GRID_STRIDE(i, n) p[i] = 0.0;
 }
 
 // Preconditioner input: s = D^-1 r in the storage precision.
 template <class T>
-__global__ void k_prep(const double* r, int64_t ldr, T* s, int64_t ldw, InvDiag invd, int64_t n,
-                       const DevState* guard, int slot0) {
+struct KPrep {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const double* r, int64_t ldr, T* s, int64_t ldw, InvDiag invd, int64_t n,
+                             const DevState* guard, int slot0);
+};
+template <class T>
+__device__ __forceinline__ void KPrep<T>::run(const double* r, int64_t ldr, T* s, int64_t ldw, InvDiag invd, int64_t n,
+                                              const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   r += slot * ldr;
@@ -483,8 +505,14 @@ __global__ void k_prep(const double* r, int64_t ldr, T* s, int64_t ldw, InvDiag 
 
 // Node blocks: s = B^-1 r in the storage precision.
 template <class T>
-__global__ void k_node_prep(const double* r, int64_t ldr, T* s, int64_t ldw, const double* binv, int64_t nodes,
-                            const DevState* guard, int slot0) {
+struct KNodePrep {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const double* r, int64_t ldr, T* s, int64_t ldw, const double* binv, int64_t nodes,
+                             const DevState* guard, int slot0);
+};
+template <class T>
+__device__ __forceinline__ void KNodePrep<T>::run(const double* r, int64_t ldr, T* s, int64_t ldw, const double* binv,
+                                                  int64_t nodes, const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   r += slot * ldr;
@@ -501,9 +529,16 @@ __global__ void k_node_prep(const double* r, int64_t ldr, T* s, int64_t ldw, con
 }
 
 // Node blocks, degree 0: z = B^-1 r / theta' (block Jacobi), optionally with (r, z), (z, q).
-__global__ void k_node_jacobi(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q,
-                              const double* binv, double inv_theta, int64_t nodes, const DevState* guard,
-                              ReduceBuf rb, int dots, int flexible, int slot0) {
+struct KNodeJacobi {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q, const double* binv,
+                             double inv_theta, int64_t nodes, const DevState* guard, ReduceBuf rb, int dots,
+                             int flexible, int slot0);
+};
+__device__ __forceinline__ void KNodeJacobi::run(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q,
+                                                 const double* binv, double inv_theta, int64_t nodes,
+                                                 const DevState* guard, ReduceBuf rb, int dots, int flexible,
+                                                 int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   r += slot * ldr;
@@ -528,9 +563,15 @@ __global__ void k_node_jacobi(const double* r, int64_t ldr, double* z, int64_t l
 
 // Degree 0: z = D^-1 r / theta' (the diagonal preconditioner), optionally with
 // the dot products (r, z), (z, q) whose finalize forms beta.
-__global__ void k_jacobi(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q, InvDiag invd,
-                         double inv_theta, int64_t n, const DevState* guard, ReduceBuf rb, int dots, int flexible,
-                         int slot0) {
+struct KJacobi {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q, InvDiag invd,
+                             double inv_theta, int64_t n, const DevState* guard, ReduceBuf rb, int dots, int flexible,
+                             int slot0);
+};
+__device__ __forceinline__ void KJacobi::run(const double* r, int64_t ldr, double* z, int64_t ldz, const double* q,
+                                             InvDiag invd, double inv_theta, int64_t n, const DevState* guard,
+                                             ReduceBuf rb, int dots, int flexible, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   r += slot * ldr;
@@ -565,9 +606,17 @@ __global__ void k_jacobi(const double* r, int64_t ldr, double* z, int64_t ldz, c
 //   MODE 2:          nothing else (the residual is refreshed before the next step).
 // The stop test runs in the finalize kernel (FinUpdate).
 template <class T, int MODE>
-__global__ void k_update(double* x, int64_t ldx, double* r, const double* p, const double* q, int64_t ldw,
-                         InvDiag invd, T* s, double* z, double inv_theta, int64_t n, const DevState* st,
-                         ReduceBuf rb, int slot0) {
+struct KUpdate {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(double* x, int64_t ldx, double* r, const double* p, const double* q, int64_t ldw,
+                             InvDiag invd, T* s, double* z, double inv_theta, int64_t n, const DevState* st,
+                             ReduceBuf rb, int slot0);
+};
+template <class T, int MODE>
+__device__ __forceinline__ void KUpdate<T, MODE>::run(double* x, int64_t ldx, double* r, const double* p,
+                                                      const double* q, int64_t ldw, InvDiag invd, T* s, double* z,
+                                                      double inv_theta, int64_t n, const DevState* st, ReduceBuf rb,
+                                                      int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   st += slot;
   if (st->done != kRunning) return;
@@ -719,11 +768,11 @@ template <class T>
 static void enqueue_prep(Handle& h, Slots sl, const double* r, int64_t ldr, const DevState* guard, hipStream_t s) {
   const int64_t n = h.n;
   if (h.bs == 3)
-    k_node_prep<T><<<dim3(flat_grid(n / 3), sl.count), kBlock, 0, s>>>(r, ldr, reinterpret_cast<T*>(h.s), h.ldw,
-                                                                        h.binv, n / 3, guard, sl.first);
+    launch<KNodePrep<T>>(dim3(flat_grid(n / 3), sl.count), kBlock, 0, s, r, ldr, reinterpret_cast<T*>(h.s), h.ldw,
+        h.binv, n / 3, guard, sl.first);
   else
-    k_prep<T><<<dim3(pair_grid(n), sl.count), kBlock, 0, s>>>(r, ldr, reinterpret_cast<T*>(h.s), h.ldw, invdiag(h),
-                                                              n, guard, sl.first);
+    launch<KPrep<T>>(dim3(pair_grid(n), sl.count), kBlock, 0, s, r, ldr, reinterpret_cast<T*>(h.s), h.ldw, invdiag(h),
+        n, guard, sl.first);
 }
 
 // Stand-alone application r -> z (caller vectors) on slot 0 of the workspace.
@@ -736,11 +785,11 @@ static void enqueue_apply_one(Handle& h, const double* r, double* z, hipStream_t
   const int64_t n = h.n;
   if (h.prm.k == 0) {
     if (h.bs == 3)
-      k_node_jacobi<<<dim3(flat_grid(n / 3), 1), kBlock, 0, s>>>(r, 0, z, 0, nullptr, h.binv, 1.0 / h.theta, n / 3,
-                                                                  nullptr, h.rb(), 0, 0, 0);
+      launch<KNodeJacobi>(dim3(flat_grid(n / 3), 1), kBlock, 0, s, r, 0, z, 0, nullptr, h.binv, 1.0 / h.theta, n / 3,
+          nullptr, h.rb(), 0, 0, 0);
     else
-      k_jacobi<<<dim3(pair_grid(n), 1), kBlock, 0, s>>>(r, 0, z, 0, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr,
-                                                        h.rb(), 0, 0, 0);
+      launch<KJacobi>(dim3(pair_grid(n), 1), kBlock, 0, s, r, 0, z, 0, nullptr, invdiag(h), 1.0 / h.theta, n, nullptr,
+          h.rb(), 0, 0, 0);
     return;
   }
   enqueue_prep<T>(h, Slots{0, 1}, r, 0, nullptr, s);
@@ -756,8 +805,14 @@ static void enqueue_apply_one(Handle& h, const double* r, double* z, hipStream_t
 
 // out = zeta in
 template <class T>
-__global__ void k_nt_scale(const T* in, T* out, int64_t ldw, double zeta, int64_t n, const DevState* guard,
-                           int slot0) {
+struct KNtScale {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const T* in, T* out, int64_t ldw, double zeta, int64_t n, const DevState* guard,
+                             int slot0);
+};
+template <class T>
+__device__ __forceinline__ void KNtScale<T>::run(const T* in, T* out, int64_t ldw, double zeta, int64_t n,
+                                                 const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   in += slot * ldw;
@@ -769,8 +824,13 @@ __global__ void k_nt_scale(const T* in, T* out, int64_t ldw, double zeta, int64_
 
 // out = zeta (2 t - out)
 template <class T>
-__global__ void k_nt_combine(const T* t, T* out, int64_t ldw, double zeta, int64_t n, const DevState* guard,
-                             int slot0) {
+struct KNtCombine {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const T* t, T* out, int64_t ldw, double zeta, int64_t n, const DevState* guard, int slot0);
+};
+template <class T>
+__device__ __forceinline__ void KNtCombine<T>::run(const T* t, T* out, int64_t ldw, double zeta, int64_t n,
+                                                   const DevState* guard, int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   t += slot * ldw;
@@ -783,9 +843,17 @@ __global__ void k_nt_combine(const T* t, T* out, int64_t ldw, double zeta, int64
 // Top level: z = zeta (2 t - w) in float64, with (r, z) and, flexible, (z, q)
 // reduced for beta (the same partials as the last recurrence step).
 template <class T>
-__global__ void k_nt_final(const T* t, const T* w, int64_t ldw, double zeta, double* z, int64_t ldz,
-                           const double* r, int64_t ldr, const double* q, int64_t n, const DevState* guard,
-                           ReduceBuf rb, int dots, int flexible, int slot0) {
+struct KNtFinal {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const T* t, const T* w, int64_t ldw, double zeta, double* z, int64_t ldz, const double* r,
+                             int64_t ldr, const double* q, int64_t n, const DevState* guard, ReduceBuf rb, int dots,
+                             int flexible, int slot0);
+};
+template <class T>
+__device__ __forceinline__ void KNtFinal<T>::run(const T* t, const T* w, int64_t ldw, double zeta, double* z,
+                                                 int64_t ldz, const double* r, int64_t ldr, const double* q, int64_t n,
+                                                 const DevState* guard, ReduceBuf rb, int dots, int flexible,
+                                                 int slot0) {
   const int slot = slot0 + int(blockIdx.y);
   if (guard && guard[slot].done != kRunning) return;
   t += slot * ldw;
@@ -813,7 +881,7 @@ static void newton_rec(Handle& h, Slots sl, int l, const T* in, T* out, const De
   const int64_t n = h.n;
   const dim3 grid(flat_grid(n), sl.count);
   if (l == 0) {
-    k_nt_scale<T><<<grid, kBlock, 0, s>>>(in, out, h.ldw, h.zeta[0], n, guard, sl.first);
+    launch<KNtScale<T>>(grid, kBlock, 0, s, in, out, h.ldw, h.zeta[0], n, guard, sl.first);
     return;
   }
   T* t1 = reinterpret_cast<T*>(h.nt[size_t(2 * l - 1)]);
@@ -821,7 +889,7 @@ static void newton_rec(Handle& h, Slots sl, int l, const T* in, T* out, const De
   newton_rec<T>(h, sl, l - 1, in, t1, guard, s);  // t1 = P_{l-1} in
   launch_bop<T>(h, InVec<T>{t1, h.ldw}, EpiStore<T>{t2, nullptr, guard, h.ldw}, sl.first, sl.count, s);
   newton_rec<T>(h, sl, l - 1, t2, out, guard, s);  // out = P_{l-1} B P_{l-1} in
-  k_nt_combine<T><<<grid, kBlock, 0, s>>>(t1, out, h.ldw, h.zeta[size_t(l)], n, guard, sl.first);
+  launch<KNtCombine<T>>(grid, kBlock, 0, s, t1, out, h.ldw, h.zeta[size_t(l)], n, guard, sl.first);
 }
 
 // z = P(B) s for the slots (s prepared in h.s), with the dot products of a solve when `dots`.
@@ -838,9 +906,10 @@ static void enqueue_newton(Handle& h, Slots sl, double* z, int64_t ldz, const do
   launch_bop<T>(h, InVec<T>{t1, h.ldw}, EpiStore<T>{t2, nullptr, guard, h.ldw}, sl.first, sl.count, s);
   newton_rec<T>(h, sl, L - 1, t2, w, guard, s);
   const uint32_t g = flat_grid(n);
-  k_nt_final<T><<<dim3(g, sl.count), kBlock, 0, s>>>(t1, w, h.ldw, h.zeta[size_t(L)], z, ldz, r, ldr, q, n, guard,
-                                                     h.rb(), dots ? 1 : 0, flexible, sl.first);
-  if (dots) k_finalize<2, FinBeta><<<sl.count, kFinThreads, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, guard, sl.first);
+  launch<KNtFinal<T>>(dim3(g, sl.count), kBlock, 0, s, t1, w, h.ldw, h.zeta[size_t(L)], z, ldz, r, ldr, q, n, guard,
+      h.rb(), dots ? 1 : 0, flexible, sl.first);
+  if (dots) launch<KFinalize<2, FinBeta>>(sl.count, kFinThreads, 0, s, FinBeta{h.st, init, flexible}, h.rb(), g, guard,
+      sl.first);
 }
 
 #define PCHEB_BY_PREC(h, FN, ...)                      \
@@ -1115,7 +1184,12 @@ static size_t footprint(const pcheb_operator* A, const pcheb_params* p, int32_t 
 
 // ================================================================ PCG internals (slot ranges)
 
-__global__ void k_init_states(DevState* st, int slot0, int count, double tol, int maxit, int flexible) {
+struct KInitStates {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(DevState* st, int slot0, int count, double tol, int maxit, int flexible);
+};
+__device__ __forceinline__ void KInitStates::run(DevState* st, int slot0, int count, double tol, int maxit,
+                                                 int flexible) {
   const int i = int(threadIdx.x);
   if (i >= count) return;
   DevState d{};
@@ -1126,7 +1200,11 @@ __global__ void k_init_states(DevState* st, int slot0, int count, double tol, in
 }
 
 // Slots that must not take part in a launch over a wider range are marked done.
-__global__ void k_retire_states(DevState* st, int slot0, int count) {
+struct KRetireStates {
+  static constexpr int kThreads = 1024;
+  __device__ static void run(DevState* st, int slot0, int count);
+};
+__device__ __forceinline__ void KRetireStates::run(DevState* st, int slot0, int count) {
   const int i = int(threadIdx.x);
   if (i < count && st[slot0 + i].done == kRunning) st[slot0 + i].done = kMaxIter;
 }
@@ -1137,15 +1215,17 @@ static void enqueue_precond(Handle& h, Slots sl, int init, int flexible, StepTim
   if (h.prm.k == 0) {
     if (h.bs == 3) {
       const uint32_t g = flat_grid(n / 3);
-      k_node_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, h.binv, 1.0 / h.theta, n / 3,
-                                                          h.st, h.rb(), 1, flexible, sl.first);
-      k_finalize<2, FinBeta><<<sl.count, kFinThreads, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
+      launch<KNodeJacobi>(dim3(g, sl.count), kBlock, 0, s, h.r, h.ldw, h.z, h.ldw, h.q, h.binv, 1.0 / h.theta, n / 3,
+          h.st, h.rb(), 1, flexible, sl.first);
+      launch<KFinalize<2, FinBeta>>(sl.count, kFinThreads, 0, s, FinBeta{h.st, init, flexible}, h.rb(), g, h.st,
+          sl.first);
       return;
     }
     const uint32_t g = pair_grid(n);
-    k_jacobi<<<dim3(g, sl.count), kBlock, 0, s>>>(h.r, h.ldw, h.z, h.ldw, h.q, invdiag(h), 1.0 / h.theta, n, h.st,
-                                                  h.rb(), 1, flexible, sl.first);
-    k_finalize<2, FinBeta><<<sl.count, kFinThreads, 0, s>>>(FinBeta{h.st, init, flexible}, h.rb(), g, h.st, sl.first);
+    launch<KJacobi>(dim3(g, sl.count), kBlock, 0, s, h.r, h.ldw, h.z, h.ldw, h.q, invdiag(h), 1.0 / h.theta, n, h.st,
+        h.rb(), 1, flexible, sl.first);
+    launch<KFinalize<2, FinBeta>>(sl.count, kFinThreads, 0, s, FinBeta{h.st, init, flexible}, h.rb(), g, h.st,
+        sl.first);
     return;
   }
   enqueue_prep<T>(h, sl, h.r, h.ldw, h.st, s);
@@ -1160,14 +1240,14 @@ static void enqueue_start(Handle& h, Slots sl, const double* b, int64_t ldb, dou
                           int flexible, StepTimer* timer, hipStream_t s) {
   const int64_t n = h.n;
   if (x0_given) {
-    k_zero_slots<<<dim3(flat_grid(n), sl.count), kBlock, 0, s>>>(h.p[0], h.ldw, n, sl.first);
+    launch<KZeroSlots>(dim3(flat_grid(n), sl.count), kBlock, 0, s, h.p[0], h.ldw, n, sl.first);
     launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, h.r, invdiag(h), h.st, nullptr, 0, ldb, h.ldw}, sl.first,
                 sl.count, s);
   } else {
     const uint32_t g = pair_grid(n);
-    k_start_zero<<<dim3(g, sl.count), kBlock, 0, s>>>(b, ldb, x, ldx, h.r, h.p[0], h.ldw, invdiag(h), n, h.rb(),
-                                                      sl.first);
-    k_finalize<2, FinStart><<<sl.count, kFinThreads, 0, s>>>(FinStart{h.st}, h.rb(), g, nullptr, sl.first);
+    launch<KStartZero>(dim3(g, sl.count), kBlock, 0, s, b, ldb, x, ldx, h.r, h.p[0], h.ldw, invdiag(h), n, h.rb(),
+        sl.first);
+    launch<KFinalize<2, FinStart>>(sl.count, kFinThreads, 0, s, FinStart{h.st}, h.rb(), g, nullptr, sl.first);
   }
   enqueue_precond<T>(h, sl, 1, flexible, timer, s);
 }
@@ -1189,7 +1269,7 @@ static void enqueue_direction(Handle& h, Slots sl, const Tz* z, const double* p_
     launch_ahat(h, InDirection<Tz>{z, p_old, st, 0.0, h.ldw}, EpiDirection{p_new, h.q, st, st, h.ldw}, sl.first,
                 sl.count, s);
   } else {
-    k_direction<<<dim3(pair_grid(h.n), sl.count), kBlock, 0, s>>>(z, p_old, p_new, h.ldw, h.n, st, sl.first);
+    launch<KDirection<Tz>>(dim3(pair_grid(h.n), sl.count), kBlock, 0, s, z, p_old, p_new, h.ldw, h.n, st, sl.first);
     launch_ahat(h, InVec<double>{p_new, h.ldw}, EpiDirection{nullptr, h.q, st, st, h.ldw}, sl.first, sl.count, s);
   }
 }
@@ -1209,27 +1289,27 @@ static void enqueue_iteration(Handle& h, Slots sl, double* x, int64_t ldx, const
   else
     enqueue_direction(h, sl, static_cast<const double*>(h.z), h.p[cur], p_new, s);
   if (refresh) {
-    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0,
-                                           n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<2>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
+    launch<KUpdate<T, 2>>(grid, kBlock, 0, s, x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0, n, st,
+        h.rb(), sl.first);
+    launch<KFinalize<3, FinUpdate<2>>>(sl.count, kFinThreads, 0, s, FinUpdate<2>{st}, h.rb(), g, st, sl.first);
     launch_ahat(h, InVec<double>{x, ldx}, EpiResidual{b, h.r, invdiag(h), st, st, 2, ldb, h.ldw}, sl.first, sl.count,
                 s);
     enqueue_precond<T>(h, sl, 0, flexible, timer, s);
     return;
   }
   if (h.bs == 3) {  // node blocks: the preconditioner input needs whole nodes, so it is a pass of its own
-    k_update<T, 2><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0,
-                                           n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<2>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<2>{st}, h.rb(), g, st, sl.first);
+    launch<KUpdate<T, 2>>(grid, kBlock, 0, s, x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, nullptr, 0.0, n, st,
+        h.rb(), sl.first);
+    launch<KFinalize<3, FinUpdate<2>>>(sl.count, kFinThreads, 0, s, FinUpdate<2>{st}, h.rb(), g, st, sl.first);
     enqueue_precond<T>(h, sl, 0, flexible, timer, s);
   } else if (h.prm.k == 0) {
-    k_update<double, 1><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, h.z,
-                                                1.0 / h.theta, n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<1>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<1>{st}, h.rb(), g, st, sl.first);
+    launch<KUpdate<double, 1>>(grid, kBlock, 0, s, x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), nullptr, h.z,
+        1.0 / h.theta, n, st, h.rb(), sl.first);
+    launch<KFinalize<3, FinUpdate<1>>>(sl.count, kFinThreads, 0, s, FinUpdate<1>{st}, h.rb(), g, st, sl.first);
   } else {
-    k_update<T, 0><<<grid, kBlock, 0, s>>>(x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), reinterpret_cast<T*>(h.s),
-                                           nullptr, 1.0 / h.theta, n, st, h.rb(), sl.first);
-    k_finalize<3, FinUpdate<0>><<<sl.count, kFinThreads, 0, s>>>(FinUpdate<0>{st}, h.rb(), g, st, sl.first);
+    launch<KUpdate<T, 0>>(grid, kBlock, 0, s, x, ldx, h.r, p_new, h.q, h.ldw, invdiag(h), reinterpret_cast<T*>(h.s),
+        nullptr, 1.0 / h.theta, n, st, h.rb(), sl.first);
+    launch<KFinalize<3, FinUpdate<0>>>(sl.count, kFinThreads, 0, s, FinUpdate<0>{st}, h.rb(), g, st, sl.first);
     if (h.prm.form == PCHEB_FORM_NEWTON)
       enqueue_newton<T>(h, sl, h.z, h.ldw, h.r, h.ldw, h.q, true, 0, flexible, st, s);
     else
@@ -1285,12 +1365,12 @@ static void enqueue_finish(Handle& h, Slots sl, const double* b, int64_t ldb, co
 // ---- exported to the serving engine (solver.hpp)
 
 void solver_init_states(Handle& h, Slots sl, double tol, int maxit, int flexible, hipStream_t s) {
-  k_init_states<<<1, std::max(1, sl.count), 0, s>>>(h.st, sl.first, sl.count, tol, maxit, flexible);
+  launch<KInitStates>(1, std::max(1, sl.count), 0, s, h.st, sl.first, sl.count, tol, maxit, flexible);
   PCHEB_HIP_CHECK(hipGetLastError());
 }
 
 void solver_retire(Handle& h, Slots sl, hipStream_t s) {
-  k_retire_states<<<1, std::max(1, sl.count), 0, s>>>(h.st, sl.first, sl.count);
+  launch<KRetireStates>(1, std::max(1, sl.count), 0, s, h.st, sl.first, sl.count);
   PCHEB_HIP_CHECK(hipGetLastError());
 }
 
@@ -1303,6 +1383,20 @@ void solver_start(Handle& h, Slots sl, const double* b, int64_t ldb, double* x, 
 void solver_iteration_pairs(Handle& h, Slots sl, double* x, int64_t ldx, int pairs, int flexible, hipStream_t s) {
   PCHEB_BY_PREC(h, enqueue_pairs_graph, h, sl, x, ldx, pairs, flexible, s);
   PCHEB_HIP_CHECK(hipGetLastError());
+}
+
+template <class T>
+static void enqueue_two_iterations(Handle& h, Slots sl, double* x, int64_t ldx, int flexible, hipStream_t s) {
+  enqueue_iteration<T>(h, sl, x, ldx, nullptr, 0, 0, flexible, false, nullptr, s);
+  enqueue_iteration<T>(h, sl, x, ldx, nullptr, 0, 1, flexible, false, nullptr, s);
+}
+
+void solver_iterations_direct(Handle& h, Slots sl, double* x, int64_t ldx, int flexible, hipStream_t s) {
+  PCHEB_BY_PREC(h, enqueue_two_iterations, h, sl, x, ldx, flexible, s);
+}
+
+void solver_apply(Handle& h, const double* r, double* z, hipStream_t s) {
+  PCHEB_BY_PREC(h, enqueue_apply_one, h, r, z, s);
 }
 
 template <class T>

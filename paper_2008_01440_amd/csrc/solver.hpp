@@ -29,6 +29,11 @@ void solver_start(Handle& h, Slots sl, const double* b, int64_t ldb, double* x, 
 void solver_prepare_graph(Handle& h, Slots sl, double* x, int64_t ldx, int flexible);
 // `pairs` x two PCG iterations of the slots, replayed from a HIP graph.
 void solver_iteration_pairs(Handle& h, Slots sl, double* x, int64_t ldx, int pairs, int flexible, hipStream_t s);
+// Two PCG iterations of the slots, launched directly (no graph); under a
+// LaunchRecorder this records the launches of an iteration pair.
+void solver_iterations_direct(Handle& h, Slots sl, double* x, int64_t ldx, int flexible, hipStream_t s);
+// z = P_k r for one vector pair (slot 0 of the workspace).
+void solver_apply(Handle& h, const double* r, double* z, hipStream_t s);
 // True residual of the slots (norms into their scalars).
 void solver_finish(Handle& h, Slots sl, const double* b, int64_t ldb, const double* x, int64_t ldx, hipStream_t s);
 // Statistics of one slot from its scalars.

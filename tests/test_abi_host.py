@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     for name in ("pcheb_setup", "pcheb_apply", "pcg_solve", "pcheb_matvec", "pcheb_destroy", "pcheb_last_error",
                  "pcheb_footprint_bytes", "pcheb_set_allocator", "pcheb_estimate_bounds",
                  "pcheb_estimate_bounds_noalloc", "pcheb_estimate_bounds_pdacg",
-                 "pcheb_estimate_bounds_block", "pserve_create",
+                 "pcheb_estimate_bounds_block", "pcheb_group_create", "pcheb_group_apply", "pcg_solve_group",
+                 "pcheb_group_destroy", "pserve_create",
                  "pserve_submit", "pserve_poll",
                  "pserve_wait", "pserve_cancel", "pserve_get_stats", "pserve_destroy"):
         assert name in fns
@@ -217,3 +218,20 @@ def test_noalloc_estimator_argument_checks():
     assert call(pc.Operator.stencil7(4), 30, v0=8) == 1 and "aligned" in pc.pcheb_last_error()
     assert call(pc.Operator.stencil7(80), 30) == 1 and "workspace" in pc.pcheb_last_error()
     assert call(pc.Operator.stencil7(79), 1001) == 1 and "nsteps" in pc.pcheb_last_error()
+
+
+def test_group_argument_checks():
+    """Group calls refuse null groups, null or repeated handles and bad counts before any device work
+    (a handle pointer is never dereferenced when the list itself is invalid)."""
+    lib = pc.load_library()
+    out = ctypes.c_void_p()
+    handles = (ctypes.c_void_p * 2)(None, None)
+    assert lib.pcheb_group_create(None, 1, ctypes.byref(out)) == 1 and "null" in pc.pcheb_last_error()
+    assert lib.pcheb_group_create(handles, 0, ctypes.byref(out)) == 1 and "count" in pc.pcheb_last_error()
+    assert lib.pcheb_group_create(handles, 1025, ctypes.byref(out)) == 1 and "count" in pc.pcheb_last_error()
+    assert lib.pcheb_group_create(handles, 2, ctypes.byref(out)) == 1 and "null handle" in pc.pcheb_last_error()
+    assert lib.pcheb_group_create(handles, 1, None) == 1
+    assert out.value is None
+    assert lib.pcheb_group_apply(None, None, None, 8, None) == 1 and "null group" in pc.pcheb_last_error()
+    assert lib.pcg_solve_group(None, None, None, 8, 1e-8, 10, 0, None, None) == 1
+    assert lib.pcheb_group_destroy(None) == 0

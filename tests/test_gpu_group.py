@@ -1,0 +1,263 @@
+"""Work lists (pcheb_group_*): several problems of one shape advanced by one launch per kernel.
+
+Every problem of a group must give, bit for bit, what its own handle gives alone (the same
+blocks do the same work), and the solutions must meet the oracle's bars.  The problems of a
+family share a shape and differ in operator values (27-point coefficient fields, elasticity
+Young's moduli, scaled 7-point CSR values) and so in their spectral bounds and recurrence
+coefficients; the 7-point stencil family differs only in its bounds.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_cases import Case, lanczos_bounds, rel_inf
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+S = 1.001
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import paper_2008_01440_amd as pc
+    pc.load_library()
+    return pc
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@functools.lru_cache(maxsize=None)
+def family(name, count=3):
+    """`count` problems of one shape with different operator values and bounds."""
+    out = []
+    for i in range(count):
+        if name == "st7":  # ragged tiles; bounds widened differently per problem
+            dims = (67, 13, 19)
+            rp, ci, v = W.stencil7_csr(*dims)
+            lo, hi = W.stencil7_bounds(*dims)
+            out.append(Case(f"st7_{i}", "stencil7", rp, ci, v, (lo * (1.0 - 0.1 * i), hi * (1.0 + 0.05 * i)),
+                            dims=dims))
+        elif name == "h27":
+            dims = (37, 11, 13)
+            kappa = W.harmonic27_kappa(*dims, seed=11 + i)
+            rp, ci, v = W.harmonic27_csr(kappa)
+            out.append(Case(f"h27_{i}", "stencil27h", rp, ci, v, lanczos_bounds(rp, ci, v), dims=dims, kappa=kappa))
+        elif name == "csr7":  # S A S with a positive diagonal S: other values, the same scaled operator
+            rp, ci, v = W.stencil7_csr(29, 23, 21)
+            sc = W.uniform(40 + i, len(rp) - 1, 0.5, 2.0)
+            rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp.astype(np.int64)))
+            out.append(Case(f"csr7_{i}", "csr", rp, ci, v * sc[rows] * sc[ci], W.stencil7_bounds(29, 23, 21)))
+        elif name in ("csr_el", "sell_el"):
+            rp, ci, v = W.elasticity_q1_csr(9, seed=2 + i)
+            out.append(Case(f"{name}_{i}", name[:-3], rp, ci, v, lanczos_bounds(rp, ci, v), sigma=1))
+        elif name == "sell_h27":
+            kappa = W.harmonic27_kappa(21, 17, 9, seed=4 + i)
+            rp, ci, v = W.harmonic27_csr(kappa)
+            out.append(Case(f"sell_h27_{i}", "sell", rp, ci, v, lanczos_bounds(rp, ci, v), sigma=256))
+        else:
+            raise KeyError(name)
+    return tuple(out)
+
+
+NAMES = ["st7", "h27", "csr7", "csr_el", "sell_el", "sell_h27"]
+
+
+def _rhs(cases, seed, zero=()):
+    n = cases[0].n
+    ld = n + (n % 2)
+    B = torch.zeros((len(cases), ld), dtype=torch.float64, device=DEV)
+    for i, c in enumerate(cases):
+        if i not in zero:
+            B[i, :n] = _t(W.rhs_from_solution(c.rp, c.ci, c.v, W.uniform(seed + i, n, -1.0, 1.0)))
+    return B
+
+
+class Handles:
+    def __init__(self, pc, cases, k, prec, fuse=1, **kw):
+        self.hs = [pc.pcheb_setup(c.operator(torch, DEV), k, c.lo, c.hi, S, prec, fuse_steps=fuse, **kw)
+                   for c in cases]
+
+    def __enter__(self):
+        return self.hs
+
+    def __exit__(self, *exc):
+        for h in self.hs:
+            h.__exit__()
+
+
+def _singles(pc, hs, B, n, **kw):
+    X, stats = [], []
+    for i, h in enumerate(hs):
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        stats.append(pc.pcg_solve(h, B[i, :n].contiguous(), x, **kw))
+        X.append(x)
+    return X, stats
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name", NAMES)
+def test_group_solve_equals_single_solves(pc, name, prec, flexible):
+    cases = family(name)
+    n = cases[0].n
+    k = 6
+    fuse = 4 if name == "st7" else 1
+    B = _rhs(cases, 100)
+    with Handles(pc, cases, k, prec, fuse) as hs:
+        with pc.pcheb_group_create(hs) as g:
+            X = torch.full_like(B, float("nan"))
+            sts = pc.pcg_solve_group(g, B[:, :n], X[:, :n], flexible=flexible)
+        Xs, singles = _singles(pc, hs, B, n, flexible=flexible)
+    for i in range(len(cases)):
+        assert torch.equal(X[i, :n], Xs[i]), (name, prec, i)
+        for key in ("iters", "status", "relres", "relres_true", "n_spmv", "n_dot"):
+            assert sts[i][key] == singles[i][key], (name, prec, i, key)
+        assert sts[i]["status"] == "OK" and sts[i]["relres_true"] <= 1.02e-8
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", NAMES)
+def test_group_apply_equals_single_applies(pc, name, prec):
+    cases = family(name)
+    n = cases[0].n
+    k = 7
+    R = torch.zeros((3, n + n % 2), dtype=torch.float64, device=DEV)
+    for i in range(3):
+        R[i, :n] = _t(W.uniform(200 + i, n, -1.0, 1.0))
+    fuse = 3 if name == "st7" else 1
+    with Handles(pc, cases, k, prec, fuse) as hs:
+        with pc.pcheb_group_create(hs) as g:
+            Z = torch.full_like(R, float("nan"))
+            pc.pcheb_group_apply(g, R[:, :n], Z[:, :n])
+            torch.cuda.synchronize()
+        for i, h in enumerate(hs):
+            z = torch.empty(n, dtype=torch.float64, device=DEV)
+            pc.pcheb_apply(h, R[i, :n].contiguous(), z)
+            torch.cuda.synchronize()
+            assert torch.equal(Z[i, :n], z), (name, prec, i)
+    if prec == "f64":
+        for i, c in enumerate(cases):
+            ref = oracle.nc_apply_unscaled(c.rp, c.ci, c.v, R[i, :n].cpu().numpy(), c.lo, c.hi, k, S)
+            assert rel_inf(Z[i, :n].cpu().numpy(), ref) <= 1e-11, (name, i)
+
+
+@pytest.mark.parametrize("name", ["h27", "csr_el", "sell_h27"])
+def test_group_solutions_match_oracle(pc, name):
+    """Each problem of an FP64 group against its own oracle solve: iterations within 2, solution
+    within 1e-6 (the single-problem bars)."""
+    cases = family(name)
+    n = cases[0].n
+    k = 10
+    B = _rhs(cases, 300)
+    with Handles(pc, cases, k, "f64") as hs, pc.pcheb_group_create(hs) as g:
+        X = torch.zeros_like(B)
+        sts = pc.pcg_solve_group(g, B[:, :n], X[:, :n], flexible=True)
+    for i, c in enumerate(cases):
+        ref = oracle.nc_pcg(c.rp, c.ci, c.v, B[i, :n].cpu().numpy(), c.lo, c.hi, k, s=S, tol=1e-8, flexible=True)
+        diff = np.linalg.norm(X[i, :n].cpu().numpy() - ref.x_hat) / np.linalg.norm(ref.x_hat)
+        print(f"{c.name}: group {sts[i]['iters']} it, oracle {ref.iters} it, rel diff {diff:.2e}")
+        assert abs(sts[i]["iters"] - ref.iters) <= 2 and diff <= 1e-6
+
+
+def test_group_newton_node_blocks_and_degree_zero(pc):
+    """The other launch sequences: Newton form (Alg. 1, k = 7), the second level on 3x3 node
+    blocks, and degree 0 (Jacobi), each grouped against single solves."""
+    st7 = family("st7")
+    el = family("csr_el")
+    for cases, kw in ((st7, dict(k=7, form="newton")), (el, dict(k=6, block_size=3)), (el, dict(k=0)),
+                      (st7, dict(k=0))):
+        n = cases[0].n
+        B = _rhs(cases, 400)
+        k = kw.pop("k")
+        lo_hi = None
+        if kw.get("block_size") == 3:  # bounds of W^T A W
+            lo_hi = []
+            for c in cases:
+                v0 = _t(W.uniform(7, n, 0.5, 1.5))
+                lo, hi = pc.pcheb_estimate_bounds(c.operator(torch, DEV), v0, 30, block_size=3)
+                lo_hi.append((lo, 1.01 * hi))
+        hs = []
+        try:
+            for i, c in enumerate(cases):
+                lo, hi = lo_hi[i] if lo_hi else (c.lo, c.hi)
+                hs.append(pc.pcheb_setup(c.operator(torch, DEV), k, lo, hi, S, "f64", **kw))
+            with pc.pcheb_group_create(hs) as g:
+                X = torch.full_like(B, float("nan"))
+                sts = pc.pcg_solve_group(g, B[:, :n], X[:, :n], flexible=True)
+            Xs, singles = _singles(pc, hs, B, n, flexible=True)
+        finally:
+            for h in hs:
+                h.__exit__()
+        for i in range(len(cases)):
+            assert torch.equal(X[i, :n], Xs[i]), (kw, k, i)
+            assert sts[i]["iters"] == singles[i]["iters"] and sts[i]["status"] == "OK"
+
+
+def test_group_rejects_problems_that_differ(pc):
+    a, b = family("h27")[:2]
+    st = family("st7")[0]
+    with pc.pcheb_setup(a.operator(torch, DEV), 6, a.lo, a.hi) as ha:
+        for other, kw, what in ((b, dict(k=7), "degree"), (b, dict(k=6, prec="f32"), "precision"),
+                                (st, dict(k=6), "operator kind")):
+            with pc.pcheb_setup(other.operator(torch, DEV), kw.pop("k"), other.lo, other.hi, S, **kw) as hb:
+                with pytest.raises(pc.PchebError) as e:
+                    pc.pcheb_group_create([ha, hb])
+                print(what, "->", e.value)
+                assert e.value.status == 1
+        with pytest.raises(pc.PchebError):
+            pc.pcheb_group_create([ha, ha])
+    # the same 7-point grid with and without fused passes makes different launches
+    with pc.pcheb_setup(st.operator(torch, DEV), 10, st.lo, st.hi, S, "f32", fuse_steps=4) as h1, \
+            pc.pcheb_setup(st.operator(torch, DEV), 10, st.lo, st.hi, S, "f32", fuse_steps=1) as h2:
+        with pytest.raises(pc.PchebError) as e:
+            pc.pcheb_group_create([h1, h2])
+        assert "differs" in str(e.value) or "launches" in str(e.value)
+
+
+def test_group_mixed_outcomes_and_graph_recapture(pc):
+    """A zero right-hand side (done before the first iteration), a problem stopped by maxit, graph
+    replay against direct launches, new vectors, and a handle whose workspace grew in between
+    (its state and iterate buffers move: the group must follow)."""
+    cases = family("h27", 4)
+    n = cases[0].n
+    B = _rhs(cases, 500, zero=(1,))
+    with Handles(pc, cases, 5, "f32") as hs, pc.pcheb_group_create(hs) as g:
+        X1 = torch.full_like(B, float("nan"))
+        sts = pc.pcg_solve_group(g, B[:, :n], X1[:, :n], flexible=True)
+        assert sts[1]["iters"] == 0 and float(X1[1, :n].abs().max()) == 0.0
+        assert all(s["status"] == "OK" for s in sts)
+        X2 = torch.full_like(B, float("nan"))
+        pc.pcg_solve_group(g, B[:, :n], X2[:, :n], flexible=True, graph=False)
+        assert torch.equal(X1[:, :n], X2[:, :n])
+        # grow problem 2's workspace (three right-hand sides), then solve the group into new vectors
+        Bm = torch.zeros((3, B.shape[1]), dtype=torch.float64, device=DEV)
+        Bm[:, :n] = B[2, :n]
+        Xm = torch.zeros_like(Bm)
+        pc.pcg_solve(hs[2], Bm[:, :n], Xm[:, :n], flexible=True)
+        X3 = torch.full_like(B, float("nan"))
+        pc.pcg_solve_group(g, B[:, :n], X3[:, :n], flexible=True)
+        assert torch.equal(X1[:, :n], X3[:, :n])
+        assert torch.equal(Xm[0, :n], X1[2, :n])
+        # maxit 3: the problems still running stop with NOT_CONVERGED, the zero one is OK
+        X4 = torch.zeros_like(B)
+        sts = pc.pcg_solve_group(g, B[:, :n], X4[:, :n], maxit=3, flexible=True)
+        assert sts[1]["status"] == "OK"
+        assert [s["status"] for i, s in enumerate(sts) if i != 1] == ["NOT_CONVERGED"] * 3
+        assert all(s["iters"] == 3 for i, s in enumerate(sts) if i != 1)
+    # a group of one problem equals its handle
+    c = cases[0]
+    with pc.pcheb_setup(c.operator(torch, DEV), 5, c.lo, c.hi, S, "f32") as h, pc.pcheb_group_create([h]) as g:
+        X = torch.zeros_like(B[:1])
+        pc.pcg_solve_group(g, B[:1, :n], X[:, :n])
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        pc.pcg_solve(h, B[0, :n].contiguous(), x)
+        assert torch.equal(X[0, :n], x)
