@@ -37,7 +37,7 @@ METRIC = "PCG solves/s + P_k(A) HBM GB/s vs FP64 plain PCG; p50/p99 solve latenc
 HBM_PEAK_GBS = 8000.0
 BF16_MAX_K = 32  # the library refuses bfloat16 recurrences of higher degree
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cheb_step_stencil7_256_traffic.md")
-KERNEL_SOURCES = ["common.hpp", "fused_stencil.hpp", "fused_launch.hpp"]  # the fused pass and its launch
+KERNEL_SOURCES = ["common.hpp", "launch.hpp", "fused_stencil.hpp", "fused_launch.hpp"]  # the fused pass and its launch
 
 
 def log(*a):
@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--nrhs-study", action="store_true",
                     help="C4 elasticity (SELL and CSR, F32, k=20): four right-hand sides in one batched solve "
                          "(matrix read once per launch) against the four solved one at a time")
+    ap.add_argument("--group-study", action="store_true",
+                    help="work lists: 16 same-shape problems with different operators solved one at a time "
+                         "against one grouped solve (27-point harmonic 32^3/64^3/96^3, elasticity 24^3)")
     ap.add_argument("--bounds", action="store_true",
                     help="compare bound estimators (Lanczos, power method + DACG, exact) on the flagship problem")
     args = ap.parse_args()
@@ -145,6 +148,9 @@ def main():
         return
     if args.nrhs_study:
         run_nrhs_study(torch, pc, W, dev)
+        return
+    if args.group_study:
+        run_group_study(torch, pc, W, dev)
         return
     configs = [c for c in args.configs.split(",") if c]
     for c in configs:
@@ -595,6 +601,78 @@ def run_nrhs_study(torch, pc, W, dev, nrhs=4, k=20):
                "speedup": round(t_single / t_batch, 3), "bitwise_equal": f"{same}/{nrhs}"}
         print(json.dumps(row), flush=True)
         log(f"  {fmt}: {nrhs} single solves {t_single:.3f}s, batched {t_batch:.3f}s, {same}/{nrhs} bitwise equal")
+
+
+def run_group_study(torch, pc, W, dev, count=16):
+    """Work lists: `count` problems of one shape with different operators, solved one after
+    another (each on its own handle, graph replay) against one grouped solve (pcheb_group_*),
+    whose launches cover every problem's tiles.  Problems: 27-point harmonic operators with
+    lognormal(0, 2) coefficient fields (seeds 1..count) on N^3 grids, N in {32, 64, 96}, and Q1
+    elasticity on 24^3 elements with Young's modulus fields (seeds 1..count), SELL-C-sigma; bounds
+    from 30 Lanczos steps each (x1.01); F32 recurrence of degree k, flexible FP64 PCG, tol 1e-8,
+    b = A x*, x* ~ U[-1, 1].  Every grouped solution must equal its single solve bit for bit.
+    One JSON line per workload."""
+    def cases():
+        for N in (32, 64, 96):
+            ops = []
+            for sd in range(1, count + 1):
+                kappa = W.harmonic27_kappa(N, N, N, seed=sd)
+                ops.append(pc.Operator.stencil27h(torch.from_numpy(kappa).to(dev)))
+            yield f"27-point harmonic {N}^3, {count} coefficient fields", ops, 30
+        ops = []
+        for sd in range(1, count + 1):
+            rp, ci, v = W.elasticity_q1_csr(24, seed=sd)
+            d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v)]
+            ops.append(pc.Operator.csr(*d, sell=True, sigma=256))
+        yield f"Q1 elasticity 24^3 elements x 3 (SELL), {count} modulus fields", ops, 20
+
+    for name, ops, k in cases():
+        n = ops[0].n
+        ld = n + (n % 2)
+        B = torch.zeros((count, ld), dtype=torch.float64, device=dev)
+        hs = []
+        for i, op in enumerate(ops):
+            v0 = torch.empty(n, dtype=torch.float64, device=dev)
+            pc.pcheb_fill_uniform(v0, 7, 0.5, 1.5)
+            lo, hi = pc.pcheb_estimate_bounds(op, v0, 30)
+            hs.append(pc.pcheb_setup(op, k, lo, 1.01 * hi, 1.001, "f32"))
+            pc.pcheb_matvec(hs[-1], torch.from_numpy(W.uniform(i, n, -1.0, 1.0)).to(dev), B[i, :n])  # b = A x*
+        try:
+            singles, t_single = [], 0.0
+            for i, h in enumerate(hs):
+                x = torch.zeros(n, dtype=torch.float64, device=dev)
+                pc.pcg_solve(h, B[i, :n].contiguous(), x, flexible=True)  # warm-up (graph capture)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = pc.pcg_solve(h, B[i, :n].contiguous(), x, flexible=True)
+                torch.cuda.synchronize()
+                t_single += time.perf_counter() - t1
+                singles.append((st, x))
+            with pc.pcheb_group_create(hs) as g:
+                X = torch.zeros_like(B)
+                pc.pcg_solve_group(g, B[:, :n], X[:, :n], flexible=True)  # warm-up (graph capture)
+                X.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sts = pc.pcg_solve_group(g, B[:, :n], X[:, :n], flexible=True)
+                torch.cuda.synchronize()
+                t_group = time.perf_counter() - t1
+        finally:
+            for h in hs:
+                pc.pcheb_destroy(h)
+        same = sum(int(torch.equal(X[i, :n], x)) for i, (_, x) in enumerate(singles))
+        iters = [s["iters"] for s, _ in singles]
+        row = {"mode": "group_study", "workload": name, "n": n, "k": k, "prec": "f32", "problems": count,
+               "iters_min": min(iters), "iters_max": max(iters),
+               "group_iters_match": all(sts[i]["iters"] == iters[i] for i in range(count)),
+               "single_solves_s": round(t_single, 4), "group_solve_s": round(t_group, 4),
+               "speedup": round(t_single / t_group, 3), "bitwise_equal": f"{same}/{count}",
+               "group_solves_per_s": round(count / t_group, 2)}
+        print(json.dumps(row), flush=True)
+        log(f"  {name}: {count} single solves {t_single:.3f}s, one group {t_group:.3f}s "
+            f"({t_single / t_group:.2f}x), iterations {min(iters)}-{max(iters)}, {same}/{count} bitwise equal")
+        del ops, B, X
+        torch.cuda.empty_cache()
 
 
 PD_POWER_STEPS = 300  # power steps for lambda_max (30 land 2.6% low on 256^3, 300 within 0.3%)
