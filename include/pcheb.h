@@ -236,7 +236,12 @@ pcheb_status pcheb_destroy(pcheb_handle h);
  * Each problem's result equals, bit for bit, that of the same call on its
  * own handle: every block does the work it does in that handle's own launch.
  * The group borrows the handles (count in [1, 1024], no duplicates); they must
- * outlive it, and while a group call runs no other call may use them.
+ * outlive it.  Group calls use the handles' workspaces: work enqueued with a
+ * handle on another stream must not overlap a group call's work (order the
+ * streams, as for two calls on one handle).  A group call first waits on the
+ * host until the device has finished the previous call of the same group (its
+ * argument tables are rewritten).  Every device block comes from the allocator
+ * of pcheb_set_allocator when one is installed.
  * Errors: INVALID, OOM, HIP.  *out is set only on OK.
  */
 typedef struct pcheb_group_s* pcheb_group;

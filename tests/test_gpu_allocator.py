@@ -1,6 +1,6 @@
 """All of the library's device memory through a caller's allocator (pcheb_set_allocator):
 counting callbacks backed by PyTorch's caching allocator see every block of a bound
-estimate, a set-up and solve, a served request and the releases; the device's free
+estimate, a set-up and solve, a work list, a served request and the releases; the device's free
 memory drops by no more than the caller's pool grows; every block comes back; and the
 allocation-free estimator calls the allocator not at all."""
 
@@ -77,6 +77,20 @@ def test_every_device_block_goes_through_the_allocator(pc):
         assert out["status"] == "OK", out
         assert al.n_alloc > before + 5
         assert not al.live and al.n_alloc == al.n_free, (al.n_alloc, al.n_free)
+
+        # a work list over two handles: its argument tables and state buffers come and go too
+        before = al.n_alloc
+        hs = [pc.pcheb_setup(op, 20, lo, 1.01 * hi, 1.001, "f32") for _ in range(2)]
+        with pc.pcheb_group_create(hs) as g:
+            B = torch.zeros((2, n), dtype=torch.float64, device=DEV)
+            B[0] = b
+            B[1] = b
+            X = torch.zeros_like(B)
+            sts = pc.pcg_solve_group(g, B, X, tol=1e-8, flexible=True)
+        assert all(s["status"] == "OK" for s in sts) and torch.equal(X[0], x_ref) and torch.equal(X[1], x_ref)
+        for hh in hs:
+            pc.pcheb_destroy(hh)
+        assert al.n_alloc >= before + 4 and not al.live, (al.n_alloc - before, al.live)
 
         # the allocation-free estimator takes nothing from the allocator
         before = al.n_alloc
