@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--nrhs-study", action="store_true",
                     help="C4 elasticity (SELL and CSR, F32, k=20): four right-hand sides in one batched solve "
                          "(matrix read once per launch) against the four solved one at a time")
+    ap.add_argument("--oracle-full", default="",
+                    help="comma-separated c3,c4: one full-size FP64 oracle solve (k = 20) on the host beside GPU "
+                         "F64 and F32 solves of the same problem")
     ap.add_argument("--group-study", action="store_true",
                     help="work lists: 16 same-shape problems with different operators solved one at a time "
                          "against one grouped solve (27-point harmonic 32^3/64^3/96^3, elasticity 24^3)")
@@ -151,6 +154,9 @@ def main():
         return
     if args.group_study:
         run_group_study(torch, pc, W, dev)
+        return
+    if args.oracle_full:
+        run_oracle_full([c for c in args.oracle_full.split(",") if c], torch, pc, W, dev)
         return
     configs = [c for c in args.configs.split(",") if c]
     for c in configs:
@@ -682,6 +688,75 @@ def run_group_study(torch, pc, W, dev, count=16):
             f"({t_single / t_group:.2f}x), iterations {min(iters)}-{max(iters)}, {same}/{count} bitwise equal")
         del ops, B, X
         torch.cuda.empty_cache()
+
+
+def run_oracle_full(which, torch, pc, W, dev, k=20):
+    """C3 (192^3 27-point harmonic, lognormal(0, 2) seed 1, matrix-free on the GPU) and C4 (Q1
+    elasticity 128^3 x 3, seed 2, SELL-C-sigma on the GPU) at full size against the FP64 C/OpenMP
+    oracle: b = A x* (x* ~ U[-1, 1], seed 0) and the bounds (30 Lanczos steps of the oracle on the
+    scaled operator from a U[0.5, 1.5) start, seed 7; lambda_max x1.01) are formed on the host and
+    passed to both sides; one oracle solve (degree k, s = 1.001, flexible, tol 1e-8) on all host
+    threads, then GPU solves with the F64 and F32 recurrences.  One JSON line per configuration
+    with iterations, oracle seconds and the GPU solutions' relative differences."""
+    import oracle
+    from oracle import omp
+
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    omp.set_threads(threads)
+    omp.set_progress(1)
+    for cfg in which:
+        t0 = time.perf_counter()
+        if cfg == "c3":
+            N = 192
+            kappa = W.harmonic27_kappa(N, N, N, seed=1)
+            rp, ci, v = W.harmonic27_csr(kappa)
+            op = pc.Operator.stencil27h(torch.from_numpy(kappa).to(dev))
+            name = "27-point harmonic diffusion 192^3, lognormal(0,2) cells seed 1 (GPU: matrix-free)"
+        elif cfg == "c4":
+            rp, ci, v = W.elasticity_q1_csr(128, seed=2)
+            d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v)]
+            op = pc.Operator.csr(*d, sell=True, sigma=256)
+            name = "Q1 elasticity 128^3 free nodes x 3, seed 2 (GPU: SELL-C-sigma, C = 64, sigma = 256)"
+        else:
+            raise SystemExit(f"--oracle-full takes c3 and c4, not {cfg}")
+        n = len(rp) - 1
+        b = W.rhs_from_solution(rp, ci, v, W.uniform(0, n, -1.0, 1.0))
+        log(f"oracle-full {cfg}: {n} unknowns, {int(rp[-1])} nonzeros built in {time.perf_counter() - t0:.1f}s")
+        a, _ = oracle.jacobi_scale(oracle.csr(rp, ci, v))
+        steps = [0]
+
+        def mv(x):
+            steps[0] += 1
+            if steps[0] % 5 == 0:
+                log(f"  oracle Lanczos step {steps[0]}")
+            return a @ x
+
+        lo, hi = oracle.lanczos_extremes(mv, W.uniform(7, n, 0.5, 1.5), 30)
+        hi *= 1.01
+        del a
+        log(f"  bounds [{lo:.6g}, {hi:.6g}]; oracle solve on {threads} thread(s)")
+        t0 = time.perf_counter()
+        ref = omp.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8, flexible=True)
+        secs = time.perf_counter() - t0
+        log(f"  oracle: {ref.iters} iterations in {secs:.1f}s, true relres {ref.relres_true:.2e}")
+        bt = torch.from_numpy(b).to(dev)
+        row = {"mode": "oracle_full", "config": cfg, "workload": name, "n": n, "nnz": int(rp[-1]), "k": k,
+               "lambda_min": lo, "lambda_max": hi, "oracle_iters": ref.iters, "oracle_seconds": round(secs, 2),
+               "oracle_threads": threads, "oracle_relres_true": ref.relres_true}
+        xr = torch.from_numpy(ref.x_hat).to(dev)
+        for prec in ("f64", "f32"):
+            with pc.pcheb_setup(op, k, lo, hi, 1.001, prec) as h:
+                x = torch.zeros(n, dtype=torch.float64, device=dev)
+                st = pc.pcg_solve(h, bt, x, tol=1e-8, flexible=True)
+            diff = float(torch.linalg.vector_norm(x - xr) / torch.linalg.vector_norm(xr))
+            row[f"gpu_{prec}"] = {"iters": st["iters"], "iters_delta": st["iters"] - ref.iters,
+                                  "rel_diff_vs_oracle": diff, "relres_true": st["relres_true"],
+                                  "meets_bar": abs(st["iters"] - ref.iters) <= 2 and diff <= 1e-6}
+            log(f"  GPU {prec}: {st['iters']} iterations, {diff:.2e} from the oracle's solution")
+        print(json.dumps(row), flush=True)
+        del rp, ci, v, b, bt, xr, op
+        torch.cuda.empty_cache()
+    omp.set_progress(0)
 
 
 PD_POWER_STEPS = 300  # power steps for lambda_max (30 land 2.6% low on 256^3, 300 within 0.3%)

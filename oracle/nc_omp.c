@@ -26,6 +26,7 @@
 #include <math.h>
 #include <omp.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -175,6 +176,11 @@ typedef struct {
 
 /* PCG with the degree-k NC preconditioner on the Jacobi-scaled system; x_hat receives the solution
  * of A_hat x_hat = b_hat.  Returns 0, or -1 if the diagonal has a non-positive entry. */
+/* Reporting only: with every > 0, ncomp_pcg prints its iteration count and recursive
+ * residual to stderr every `every` iterations (long solves then show progress). */
+static int g_progress = 0;
+void ncomp_set_progress(int every) { g_progress = every > 0 ? every : 0; }
+
 int ncomp_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val, const double* b_hat,
               double lmin, double lmax, int k, double s, double tol, int maxit, int flexible, double* x_hat,
               ncomp_stats* st) {
@@ -233,6 +239,10 @@ int ncomp_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const double
       const double rnorm = sqrt(dot(n, r, r));
       ++ndot;
       relres = rnorm / bnorm;
+      if (g_progress > 0 && it % g_progress == 0) {
+        fprintf(stderr, "oracle iteration %d: relres %.3e\n", it, relres);
+        fflush(stderr);
+      }
       if (!isfinite(rnorm)) {
         breakdown = 1;
         break;

@@ -63,6 +63,7 @@ def _declare(lib):
     lib.ncomp_apply_unscaled.argtypes = [i64, vp, vp, vp, vp, f64, f64, ctypes.c_int, f64, vp]
     lib.ncomp_apply_unscaled.restype = ctypes.c_int
     lib.ncomp_set_threads.argtypes = [ctypes.c_int]
+    lib.ncomp_set_progress.argtypes = [ctypes.c_int]
     lib.ncomp_max_threads.restype = ctypes.c_int
     return lib
 
@@ -70,6 +71,11 @@ def _declare(lib):
 def set_threads(n: int) -> None:
     """Host threads of the following calls."""
     load().ncomp_set_threads(int(n))
+
+
+def set_progress(every: int) -> None:
+    """Print the iteration count and residual to stderr every `every` PCG iterations (0: never)."""
+    load().ncomp_set_progress(int(every))
 
 
 def max_threads() -> int:

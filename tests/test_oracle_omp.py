@@ -116,6 +116,24 @@ def test_thread_count_only_changes_rounding():
     omp.set_threads(4)
 
 
+def test_progress_lines_report_without_changing_the_solve(capfd):
+    """set_progress only prints: the same bits with and without it, one line per iteration."""
+    rp, ci, v = W.stencil7_csr(12, 11, 10)
+    lo, hi = W.stencil7_bounds(12, 11, 10)
+    b = W.uniform(6, len(rp) - 1, -1.0, 1.0)
+    omp.set_threads(2)
+    quiet = omp.nc_pcg(rp, ci, v, b, lo, hi, 5, flexible=True)
+    omp.set_progress(1)
+    try:
+        loud = omp.nc_pcg(rp, ci, v, b, lo, hi, 5, flexible=True)
+    finally:
+        omp.set_progress(0)
+        omp.set_threads(4)
+    lines = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("oracle iteration")]
+    assert np.array_equal(quiet.x_hat, loud.x_hat) and quiet.iters == loud.iters
+    assert len(lines) == loud.iters and lines[-1].startswith(f"oracle iteration {loud.iters}:")
+
+
 MUTANTS = [
     ("c->rho[j] = 1.0 / (2.0 * c->sigma - c->rho[j - 1]);", "c->rho[j] = 1.0 / (2.0 * c->sigma + c->rho[j - 1]);",
      "rho recurrence sign"),
