@@ -307,3 +307,52 @@ def test_solve_elasticity_128_matches_f64(pc):
     st64, x64 = _solve(pc, op, b, 20, lo, 1.01 * hi, "f64")
     st, x = _solve(pc, op, b, 20, lo, 1.01 * hi, "f32")
     _agree(st, x, st64, x64, "elasticity 128^3 SELL k=20 F32")
+
+
+def _oracle_threads():
+    import os
+    return int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+
+
+def _against_oracle(pc, op, rp, ci, v, lo, hi, k, what):
+    """One FP64 C/OpenMP oracle solve (flexible, s = 1.001, tol 1e-8) of A_hat x = A_hat x*, x* ~
+    U[-1, 1] seed 0, formed on the host; GPU F64 and F32 solves of the same system within +-2
+    iterations and 1e-6 of the oracle's solution."""
+    from oracle import omp
+    n = len(rp) - 1
+    b = W.rhs_from_solution(rp, ci, v, W.uniform(0, n, -1.0, 1.0))
+    omp.set_threads(_oracle_threads())
+    ref = omp.nc_pcg(rp, ci, v, b, lo, hi, k, s=1.001, tol=1e-8, flexible=True)
+    assert ref.converged
+    bt = torch.from_numpy(b).to(DEV)
+    xr = torch.from_numpy(ref.x_hat).to(DEV)
+    for prec in ("f64", "f32"):
+        st, x = _solve(pc, op, bt, k, lo, hi, prec)
+        d = float(torch.linalg.vector_norm(x - xr) / torch.linalg.vector_norm(xr))
+        print(f"{what} {prec}: {st['iters']} iterations (oracle {ref.iters}), {d:.2e} from the oracle", flush=True)
+        assert st["status"] == "OK" and st["relres_true"] <= 1.02e-8
+        assert abs(st["iters"] - ref.iters) <= 2 and d <= 1e-6, (what, prec, st["iters"], ref.iters, d)
+
+
+def test_solve_h27_192_matches_oracle(pc):
+    """C3 at full size (192^3 27-point harmonic, lognormal(0, 2) seed 1, k = 20) against the CPU
+    oracle on the CSR form of the same operator, with the fixed interval [1e-4, 2] (it contains the
+    Jacobi-scaled spectrum) on both sides."""
+    N = 192
+    kappa = W.harmonic27_kappa(N, N, N, seed=1)
+    rp, ci, v = W.harmonic27_csr(kappa)
+    op = pc.Operator.stencil27h(torch.from_numpy(kappa).to(DEV))
+    _against_oracle(pc, op, rp, ci, v, 1e-4, 2.0, 20, "192^3 27-point k=20")
+
+
+def test_solve_elasticity_128_matches_oracle(pc):
+    """C4 at full size (Q1 elasticity 128^3 x 3, 502M nonzeros, SELL-C-sigma on the GPU, k = 20)
+    against the CPU oracle.  Interval: lambda_max from the scaled matrix's largest absolute row sum
+    (a Gershgorin bound, computed on the host), lambda_min = 1e-3."""
+    _, rp, ci, v = _elasticity_128()
+    d = [torch.from_numpy(a).to(DEV) for a in (rp, ci, v)]
+    op = pc.Operator.csr(*d, sell=True, sigma=256)
+    a, _ = oracle.jacobi_scale(oracle.csr(rp, ci, v))
+    hi = float(np.abs(a).sum(axis=1).max())
+    del a
+    _against_oracle(pc, op, rp, ci, v, 1e-3, hi, 20, "elasticity 128^3 SELL k=20")
