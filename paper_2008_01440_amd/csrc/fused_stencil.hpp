@@ -349,6 +349,19 @@ __device__ __forceinline__ void KFusedPass64<S, TY, NT>::run(const double* __res
   auto ld64 = [](__amdgpu_buffer_rsrc_t r, int off, int soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
   };
+  // Level l (2 .. S + 1) is needed only on region rows l - 1 .. RY - l: the rows
+  // beyond are read by no point of level l + 1.  act[l - 2][m] marks owned
+  // point m inside them; wavefronts whose points all lie outside skip the level
+  // (its arithmetic, LDS writes and neighbour reads), and the values they leave
+  // stale are never read.
+  bool act[S][P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int p = tid + NT * m;
+    const int ry = p / RX;
+#pragma unroll
+    for (int l = 2; l <= S + 1; ++l) act[l - 2][m] = p < NP && ry >= l - 1 && ry <= RY - l;
+  }
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
     const int tx = int(t % tiles_x);
@@ -429,11 +442,16 @@ __device__ __forceinline__ void KFusedPass64<S, TY, NT>::run(const double* __res
       }
       if (adv + 1 < nadv) fetch(zs + adv + 1, zs + adv);
       double nbs[2][P];
+      // level l computes plane zs + adv - (l - 1); below z0 - (S + 1 - l) no plane of the
+      // next level reads it (the pipeline's first steps fill the levels from below)
+      auto needed = [&](int l) { return zs + adv - (l - 1) >= z0 - (S + 1 - l); };
       auto read_sums = [&](auto level, double* out) {
         constexpr int l = decltype(level)::value;  // sums of level l - 1's plane from the previous step
         const double* b = lds[l - 2][PAR ^ 1];
+        if (!needed(l)) return;
 #pragma unroll
-        for (int m = 0; m < P; ++m) out[m] = (b[q[m] - 1] + b[q[m] + 1]) + (b[q[m] - RX] + b[q[m] + RX]);
+        for (int m = 0; m < P; ++m)
+          if (act[l - 2][m]) out[m] = (b[q[m] - 1] + b[q[m] + 1]) + (b[q[m] - RX] + b[q[m] + RX]);
       };
       read_sums(std::integral_constant<int, 2>{}, nbs[0]);
 #pragma unroll
@@ -446,34 +464,33 @@ __device__ __forceinline__ void KFusedPass64<S, TY, NT>::run(const double* __res
         const bool zin = z >= 0 && z < nz;
         const double a = cf.a[l - 2], b = cf.b[l - 2], c = cf.c[l - 2];
         if constexpr (l + 1 <= S + 1) read_sums(std::integral_constant<int, l + 1>{}, nbs[(l - 1) & 1]);
-        double v[P];
-        if (zin) {
+        if (!zin) {  // a plane outside the grid: zeros
+          if constexpr (l <= S) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+              L[li][K0][m] = 0.0;
+              lds[li][PAR][q[m]] = 0.0;
+            }
+          }
+        } else if (needed(l)) {
+          const bool st = l >= S && z >= z0 && z < z1;
+          const auto ro = l == S ? r_ob : r_oa;
+          const int so = (z - zlo) * plane_bytes;
 #pragma unroll
           for (int m = 0; m < P; ++m) {
+            if (!act[l - 2][m]) continue;
             const double yc = L[l - 2][K1][m];
             double nb = nbs[l & 1][m];
             nb += L[l - 2][K0][m] + L[l - 2][K2][m];
             const double yprev = (l == 2) ? nyb[m] : L[lp][K2][m];
             double w = a * yc + c * (sr[l - 2][m] - (yc - nb * sixth));  // same order as EpiChebStep
             w -= b * yprev;
-            v[m] = dom[m] ? w : 0.0;
-          }
-          if (l >= S && z >= z0 && z < z1) {
-            const auto ro = l == S ? r_ob : r_oa;
-            const int so = (z - zlo) * plane_bytes;
-#pragma unroll
-            for (int m = 0; m < P; ++m)
-              __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[m]), ro, sto[m], so, 0);
-          }
-        } else {
-#pragma unroll
-          for (int m = 0; m < P; ++m) v[m] = 0.0;
-        }
-        if constexpr (l <= S) {
-#pragma unroll
-          for (int m = 0; m < P; ++m) {
-            L[li][K0][m] = v[m];
-            lds[li][PAR][q[m]] = v[m];
+            const double v = dom[m] ? w : 0.0;
+            if (st) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), ro, sto[m], so, 0);
+            if constexpr (l <= S) {
+              L[li][K0][m] = v;
+              lds[li][PAR][q[m]] = v;
+            }
           }
         }
       };
