@@ -92,8 +92,11 @@ def main():
     ap.add_argument("--cpu-oracle", default="omp", choices=["omp", "numpy"],
                     help="oracle of the CPU baseline and the parity check: C/OpenMP (all host threads and one) "
                          "or numpy/scipy (one thread)")
-    ap.add_argument("--no-variants", action="store_true", help="time the flagship only")
+    ap.add_argument("--no-variants", action="store_true", help="time the flagship only (no variants, no batching leg)")
     ap.add_argument("--no-serve", action="store_true", help="skip the short serving leg")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the short batching leg (four right-hand sides of a 64^3 elasticity operator in one "
+                         "solve; 16 27-point operators of 32^3 and 64^3 in one grouped solve)")
     ap.add_argument("--bench-serve-requests", type=int, default=200,
                     help="requests of the serving leg of the default run (50 req/s)")
     ap.add_argument("--serve", action="store_true",
@@ -341,6 +344,18 @@ def main():
 
     roofline = roofline_of(flag)
 
+    batching = None
+    if not (args.no_batching or args.no_variants):  # --no-variants: the flagship alone
+        log("batching: several right-hand sides of one operator, several operators of one shape")
+        keep = ("workload", "format", "n", "k", "prec", "nrhs", "problems", "single_solves_s", "batched_solve_s",
+                "group_solve_s", "speedup", "bitwise_equal")
+        batching = {
+            "multi_rhs": [{kk: r[kk] for kk in keep if kk in r}
+                          for r in run_nrhs_study(torch, pc, W, dev, N=64, formats=("sell256",), emit=False)],
+            "work_list": [{kk: r[kk] for kk in keep if kk in r}
+                          for r in run_group_study(torch, pc, W, dev, sizes=(32, 64), elasticity=None, emit=False)],
+        }
+
     serving = None
     if not args.no_serve:
         log("serving:")
@@ -405,6 +420,8 @@ def main():
         for name, r in variants.items():
             if r["kind"] == "stencil7" and r["k"] >= 3 and r["step_avg_us"]:
                 out.setdefault("roofline_by_variant", {})[name] = roofline_of(r)
+    if batching:
+        out["batching"] = batching
     if serving:
         out["serving"] = serving
     print(json.dumps(out))
@@ -563,13 +580,13 @@ def run_c4(torch, pc, W, dev):
           flush=True)
 
 
-def run_nrhs_study(torch, pc, W, dev, nrhs=4, k=20):
-    """Q1 elasticity 128^3 x 3 (C4), F32 recurrence of degree k, flexible FP64 PCG, tol 1e-8:
-    nrhs right-hand sides b_j = A x*_j (x*_j ~ U[-1, 1], seeds 0..nrhs-1) solved in one batched
+def run_nrhs_study(torch, pc, W, dev, nrhs=4, k=20, N=128, formats=("sell256", "csr"), emit=True):
+    """Q1 elasticity N^3 x 3 (C4 at N = 128), F32 recurrence of degree k, flexible FP64 PCG, tol
+    1e-8: nrhs right-hand sides b_j = A x*_j (x*_j ~ U[-1, 1], seeds 0..nrhs-1) solved in one batched
     call, whose CSR / SELL launches read the matrix once for every four of them, against the same
     right-hand sides solved one at a time.  Each batched solution must equal its single solve
-    bit for bit.  One JSON line per operator format."""
-    N = 128
+    bit for bit.  One JSON line per operator format (emit), and the rows returned."""
+    rows = []
     t0 = time.perf_counter()
     rp, ci, v = W.elasticity_q1_csr(N, seed=2)
     n = len(rp) - 1
@@ -588,7 +605,7 @@ def run_nrhs_study(torch, pc, W, dev, nrhs=4, k=20):
     lo, hi = pc.pcheb_estimate_bounds(pc.Operator.csr(*d), v0, 30)
     hi *= 1.01
     del v0
-    for fmt in ("sell256", "csr"):
+    for fmt in formats:
         op = pc.Operator.csr(*d, sell=fmt != "csr", sigma=256)
         with pc.pcheb_setup(op, k, lo, hi, 1.001, "f32") as h:
             X = torch.zeros((nrhs, ld), dtype=torch.float64, device=dev)
@@ -610,15 +627,21 @@ def run_nrhs_study(torch, pc, W, dev, nrhs=4, k=20):
             torch.cuda.synchronize()
             t_batch = time.perf_counter() - t1
         same = sum(int(torch.equal(X[j, :n], x)) for j, (_, x) in enumerate(singles))
-        row = {"mode": "nrhs_study", "format": fmt, "n": n, "k": k, "prec": "f32", "nrhs": nrhs,
+        row = {"mode": "nrhs_study", "workload": f"Q1 elasticity {N}^3 free nodes x 3, seed 2", "format": fmt,
+               "n": n, "k": k, "prec": "f32", "nrhs": nrhs,
                "iters": [s["iters"] for s, _ in singles], "batched_iters": stb["iters"],
                "single_solves_s": round(t_single, 4), "batched_solve_s": round(t_batch, 4),
                "speedup": round(t_single / t_batch, 3), "bitwise_equal": f"{same}/{nrhs}"}
-        print(json.dumps(row), flush=True)
+        if emit:
+            print(json.dumps(row), flush=True)
+        rows.append(row)
         log(f"  {fmt}: {nrhs} single solves {t_single:.3f}s, batched {t_batch:.3f}s, {same}/{nrhs} bitwise equal")
+    del d
+    torch.cuda.empty_cache()
+    return rows
 
 
-def run_group_study(torch, pc, W, dev, count=16):
+def run_group_study(torch, pc, W, dev, count=16, sizes=(32, 64, 96), elasticity=24, emit=True):
     """Work lists: `count` problems of one shape with different operators, solved one after
     another (each on its own handle, graph replay) against one grouped solve (pcheb_group_*),
     whose launches cover every problem's tiles.  Problems: 27-point harmonic operators with
@@ -628,19 +651,22 @@ def run_group_study(torch, pc, W, dev, count=16):
     b = A x*, x* ~ U[-1, 1].  Every grouped solution must equal its single solve bit for bit.
     One JSON line per workload."""
     def cases():
-        for N in (32, 64, 96):
+        for N in sizes:
             ops = []
             for sd in range(1, count + 1):
                 kappa = W.harmonic27_kappa(N, N, N, seed=sd)
                 ops.append(pc.Operator.stencil27h(torch.from_numpy(kappa).to(dev)))
             yield f"27-point harmonic {N}^3, {count} coefficient fields", ops, 30
+        if not elasticity:
+            return
         ops = []
         for sd in range(1, count + 1):
-            rp, ci, v = W.elasticity_q1_csr(24, seed=sd)
+            rp, ci, v = W.elasticity_q1_csr(elasticity, seed=sd)
             d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v)]
             ops.append(pc.Operator.csr(*d, sell=True, sigma=256))
-        yield f"Q1 elasticity 24^3 elements x 3 (SELL), {count} modulus fields", ops, 20
+        yield f"Q1 elasticity {elasticity}^3 elements x 3 (SELL), {count} modulus fields", ops, 20
 
+    rows = []
     for name, ops, k in cases():
         n = ops[0].n
         ld = n + (n % 2)
@@ -683,11 +709,14 @@ def run_group_study(torch, pc, W, dev, count=16):
                "single_solves_s": round(t_single, 4), "group_solve_s": round(t_group, 4),
                "speedup": round(t_single / t_group, 3), "bitwise_equal": f"{same}/{count}",
                "group_solves_per_s": round(count / t_group, 2)}
-        print(json.dumps(row), flush=True)
+        if emit:
+            print(json.dumps(row), flush=True)
+        rows.append(row)
         log(f"  {name}: {count} single solves {t_single:.3f}s, one group {t_group:.3f}s "
             f"({t_single / t_group:.2f}x), iterations {min(iters)}-{max(iters)}, {same}/{count} bitwise equal")
         del ops, B, X
         torch.cuda.empty_cache()
+    return rows
 
 
 def run_oracle_full(which, torch, pc, W, dev, k=20):
