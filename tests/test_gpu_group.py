@@ -261,3 +261,34 @@ def test_group_mixed_outcomes_and_graph_recapture(pc):
         x = torch.zeros(n, dtype=torch.float64, device=DEV)
         pc.pcg_solve(h, B[0, :n].contiguous(), x)
         assert torch.equal(X[0, :n], x)
+
+
+def test_group_of_300_small_problems(pc):
+    """300 problems in one group (grid dimension z = 300; the state gather spans two blocks):
+    7-point 9 x 7 x 5 grids whose bounds differ, so every problem has its own recurrence
+    coefficients, and a few converging at other iterations (right-hand sides of different scales
+    and one zero).  Every solution equals its single solve bit for bit."""
+    dims = (9, 7, 5)
+    n = dims[0] * dims[1] * dims[2]
+    lo, hi = W.stencil7_bounds(*dims)
+    count = 300
+    ld = n + n % 2
+    B = torch.zeros((count, ld), dtype=torch.float64, device=DEV)
+    for i in range(count):
+        if i != 17:
+            B[i, :n] = _t(W.uniform(1000 + i, n, -1.0, 1.0) * (1.0 + (i % 7)))
+    hs = [pc.pcheb_setup(pc.Operator.stencil7(*dims), 6, lo * (1.0 - 0.002 * i), hi * (1.0 + 0.001 * i), S, "f32")
+          for i in range(count)]
+    try:
+        with pc.pcheb_group_create(hs) as g:
+            X = torch.full_like(B, float("nan"))
+            sts = pc.pcg_solve_group(g, B[:, :n], X[:, :n], flexible=True)
+        for i, h in enumerate(hs):
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            st = pc.pcg_solve(h, B[i, :n].contiguous(), x, flexible=True)
+            assert torch.equal(X[i, :n], x), i
+            assert sts[i]["iters"] == st["iters"] and sts[i]["status"] == st["status"] == "OK", i
+    finally:
+        for h in hs:
+            h.__exit__()
+    assert sts[17]["iters"] == 0
