@@ -117,9 +117,9 @@ def main():
     ap.add_argument("--nrhs-study", action="store_true",
                     help="C4 elasticity (SELL and CSR, F32, k=20): four right-hand sides in one batched solve "
                          "(matrix read once per launch) against the four solved one at a time")
-    ap.add_argument("--oracle-full", default="",
-                    help="comma-separated c3,c4: one full-size FP64 oracle solve (k = 20) on the host beside GPU "
-                         "F64 and F32 solves of the same problem")
+    ap.add_argument("--cpu-baseline-configs", default="",
+                    help="comma-separated c3,c4: the CPU baseline at full size, one FP64 oracle solve (k = 20) on "
+                         "the host threads, beside GPU F64 and F32 solves of the same problem")
     ap.add_argument("--group-study", action="store_true",
                     help="work lists: 16 same-shape problems with different operators solved one at a time "
                          "against one grouped solve (27-point harmonic 32^3/64^3/96^3, elasticity 24^3)")
@@ -158,8 +158,8 @@ def main():
     if args.group_study:
         run_group_study(torch, pc, W, dev)
         return
-    if args.oracle_full:
-        run_oracle_full([c for c in args.oracle_full.split(",") if c], torch, pc, W, dev)
+    if args.cpu_baseline_configs:
+        cpu_baseline_configs([c for c in args.cpu_baseline_configs.split(",") if c], torch, pc, W, dev)
         return
     configs = [c for c in args.configs.split(",") if c]
     for c in configs:
@@ -719,8 +719,8 @@ def run_group_study(torch, pc, W, dev, count=16, sizes=(32, 64, 96), elasticity=
     return rows
 
 
-def run_oracle_full(which, torch, pc, W, dev, k=20):
-    """C3 (192^3 27-point harmonic, lognormal(0, 2) seed 1, matrix-free on the GPU) and C4 (Q1
+def cpu_baseline_configs(which, torch, pc, W, dev, k=20):
+    """The CPU baseline of C3 and C4 at full size, with parity: C3 (192^3 27-point harmonic, lognormal(0, 2) seed 1, matrix-free on the GPU) and C4 (Q1
     elasticity 128^3 x 3, seed 2, SELL-C-sigma on the GPU) at full size against the FP64 C/OpenMP
     oracle: b = A x* (x* ~ U[-1, 1], seed 0) and the bounds (30 Lanczos steps of the oracle on the
     scaled operator from a U[0.5, 1.5) start, seed 7; lambda_max x1.01) are formed on the host and
@@ -747,10 +747,10 @@ def run_oracle_full(which, torch, pc, W, dev, k=20):
             op = pc.Operator.csr(*d, sell=True, sigma=256)
             name = "Q1 elasticity 128^3 free nodes x 3, seed 2 (GPU: SELL-C-sigma, C = 64, sigma = 256)"
         else:
-            raise SystemExit(f"--oracle-full takes c3 and c4, not {cfg}")
+            raise SystemExit(f"--cpu-baseline-configs takes c3 and c4, not {cfg}")
         n = len(rp) - 1
         b = W.rhs_from_solution(rp, ci, v, W.uniform(0, n, -1.0, 1.0))
-        log(f"oracle-full {cfg}: {n} unknowns, {int(rp[-1])} nonzeros built in {time.perf_counter() - t0:.1f}s")
+        log(f"cpu baseline {cfg}: {n} unknowns, {int(rp[-1])} nonzeros built in {time.perf_counter() - t0:.1f}s")
         a, _ = oracle.jacobi_scale(oracle.csr(rp, ci, v))
         steps = [0]
 
@@ -769,7 +769,7 @@ def run_oracle_full(which, torch, pc, W, dev, k=20):
         secs = time.perf_counter() - t0
         log(f"  oracle: {ref.iters} iterations in {secs:.1f}s, true relres {ref.relres_true:.2e}")
         bt = torch.from_numpy(b).to(dev)
-        row = {"mode": "oracle_full", "config": cfg, "workload": name, "n": n, "nnz": int(rp[-1]), "k": k,
+        row = {"mode": "cpu_baseline_full_size", "config": cfg, "workload": name, "n": n, "nnz": int(rp[-1]), "k": k,
                "lambda_min": lo, "lambda_max": hi, "oracle_iters": ref.iters, "oracle_seconds": round(secs, 2),
                "oracle_threads": threads, "oracle_relres_true": ref.relres_true}
         xr = torch.from_numpy(ref.x_hat).to(dev)
