@@ -165,13 +165,12 @@ __device__ __forceinline__ void KFusedPass<S, TY, NT, T>::run(const T* __restric
     const auto r_oa = tile_rsrc(out_a), r_ob = tile_rsrc(out_b);
     auto plane_soff = [&](int zz) { return zz >= 0 && zz < nz ? (zz - zlo) * plane_bytes : 0; };
 
-    // owned points p = tid + NT m: top[m] is the highest level whose region
-    // contains the point (0 outside the grid or for p >= NP); dom[m] says the
-    // point is in the grid; ldo[m] / sto[m] are the byte offsets of its loads
-    // and output stores in a plane (out of range where there is nothing to
-    // load or store); q[m] is its LDS index (lanes without a point use the
-    // first entry of the tail margin, which no point with a valid value reads).
-    int top[P], q[P], ldo[P], sto[P];
+    // owned points p = tid + NT m: dom[m] says the point is in the grid;
+    // ldo[m] / sto[m] are the byte offsets of its loads and output stores in a
+    // plane (out of range where there is nothing to load or store); q[m] is its
+    // LDS index (lanes without a point use the first entry of the tail margin,
+    // which no point with a valid value reads).
+    int q[P], ldo[P], sto[P];
     bool dom[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
@@ -179,9 +178,6 @@ __device__ __forceinline__ void KFusedPass<S, TY, NT, T>::run(const T* __restric
       const int ry = p / RX, rx = p - (p / RX) * RX;
       const int gx = x0 + rx, gy = y0 + ry;
       dom[m] = p < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-      const int lx = rx + 1 < RX - rx ? rx + 1 : RX - rx;
-      const int ly = ry + 1 < RY - ry ? ry + 1 : RY - ry;
-      top[m] = dom[m] ? (lx < ly ? lx : ly) : 0;
       const bool inner = dom[m] && rx >= S && rx < S + TX && ry >= S && ry < S + TY;
       ldo[m] = dom[m] ? (gx + nx * gy) * E : kOutOfRange;
       sto[m] = inner ? (gx + nx * gy) * E : kOutOfRange;
