@@ -76,8 +76,10 @@ static void merge(const std::vector<LaunchRecorder>& recs, const char* what, Pha
                                 " differs from problem 0's in kernel, grid or block (the problems differ in shape "
                                 "or parameters)");
     }
-    const size_t stride = round_up_bytes(a.args.size(), 16);
-    const size_t off = round_up_bytes(table.size(), std::max<size_t>(16, a.align));
+    // every problem's pack at the pack type's alignment (at least 16 bytes)
+    const size_t al = std::max<size_t>(16, a.align);
+    const size_t stride = round_up_bytes(a.args.size(), al);
+    const size_t off = round_up_bytes(table.size(), al);
     table.resize(off + stride * count);
     for (size_t i = 0; i < count; ++i)
       std::memcpy(table.data() + off + i * stride, recs[i].list[j].args.data(), a.args.size());
