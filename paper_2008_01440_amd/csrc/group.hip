@@ -107,7 +107,7 @@ struct Group {
   bool done_recorded = false;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
-  std::vector<unsigned char> graph_args;  // the pair phase's table the graph was captured with
+  Phase graph_phase;  // the pair phase's launches the graph was captured with
   const void* graph_table = nullptr;
 
   const DevState* const* state_ptrs() const { return static_cast<const DevState* const*>(states.ptr); }
@@ -158,11 +158,25 @@ static void upload(Group& g, const std::vector<unsigned char>& table, hipStream_
 
 static const unsigned char* dtab(const Group& g) { return static_cast<const unsigned char*>(g.table.ptr); }
 
-// The iteration pair as a graph of work-list launches; captured again when its
-// table changed (other vectors, flags, or a handle's workspace reallocated).
-static void ensure_graph(Group& g, const Phase& pair, const std::vector<unsigned char>& table) {
-  const std::vector<unsigned char> args(table.begin() + int64_t(pair.begin), table.begin() + int64_t(pair.end));
-  if (g.graph && g.graph_table == g.table.ptr && g.graph_args == args) return;
+static bool same_launches(const Phase& a, const Phase& b) {
+  if (a.entries.size() != b.entries.size()) return false;
+  for (size_t j = 0; j < a.entries.size(); ++j) {
+    const Phase::Entry& x = a.entries[j];
+    const Phase::Entry& y = b.entries[j];
+    if (x.fn != y.fn || !same_dim(x.grid, y.grid) || !same_dim(x.block, y.block) || x.shmem != y.shmem ||
+        x.offset != y.offset || x.stride != y.stride)
+      return false;
+  }
+  return true;
+}
+
+// The iteration pair as a graph of work-list launches.  Its kernel nodes hold
+// only table addresses; the argument packs (vectors, flags, workspace) are read
+// from the table, which every call uploads before the first replay.  So the
+// graph is captured again only when the launches change (kernels, grids, table
+// offsets) or the table was reallocated.
+static void ensure_graph(Group& g, const Phase& pair) {
+  if (g.graph && g.graph_table == g.table.ptr && same_launches(g.graph_phase, pair)) return;
   if (!g.capture_stream) PCHEB_HIP_CHECK(hipStreamCreateWithFlags(&g.capture_stream, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   PCHEB_HIP_CHECK(hipStreamBeginCapture(g.capture_stream, hipStreamCaptureModeRelaxed));
@@ -180,7 +194,7 @@ static void ensure_graph(Group& g, const Phase& pair, const std::vector<unsigned
   PCHEB_HIP_CHECK(e);
   if (g.graph) (void)hipGraphExecDestroy(g.graph);
   g.graph = exec;
-  g.graph_args = args;
+  g.graph_phase = pair;
   g.graph_table = g.table.ptr;
 }
 
@@ -307,7 +321,7 @@ static pcheb_status group_solve(Group& g, const double* b, double* x, int64_t ld
   merge(record(g, [&](Handle& h, int i) { solver_finish(h, one, bi(i), ld, xi(i), ld, s); }), "true residual",
         finish, table);
   upload(g, table, s);
-  if (use_graph) ensure_graph(g, pair, table);
+  if (use_graph) ensure_graph(g, pair);
 
   enqueue_phase(init, dtab(g), g.count, s);
   enqueue_phase(start, dtab(g), g.count, s);

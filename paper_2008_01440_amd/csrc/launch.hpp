@@ -22,6 +22,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -106,7 +107,10 @@ struct KernelParams<void (*)(P...)> {
   static void go(dim3 grid, dim3 block, size_t shmem, hipStream_t s, std::decay_t<P>... a) {
     if (LaunchRecorder* rec = launch_recorder()) {
       static_assert(std::is_trivially_copyable<pack>::value, "kernel arguments are copied as bytes");
-      const pack pk{{a}...};
+      // built in zeroed storage so padding bytes are zero and equal argument
+      // values give equal bytes (work-list graphs are keyed on these bytes)
+      alignas(pack) unsigned char raw[sizeof(pack)] = {};
+      new (raw) pack{{a}...};
       LaunchRecord r;
       r.kernel = reinterpret_cast<const void*>(&k_group<K, pack>);
       r.launch_group = &group_fn<K>;
@@ -115,7 +119,7 @@ struct KernelParams<void (*)(P...)> {
       r.shmem = shmem;
       r.align = alignof(pack);
       r.args.resize(sizeof(pack));
-      std::memcpy(r.args.data(), &pk, sizeof(pack));
+      std::memcpy(r.args.data(), raw, sizeof(pack));
       rec->list.push_back(std::move(r));
       return;
     }
