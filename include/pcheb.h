@@ -148,8 +148,9 @@ typedef struct pcg_stats {
   int64_t n_spmv;           /* operator products, preconditioner included */
   int64_t n_dot;            /* scalar products, counted as in Table 3 of the paper */
   double seconds;           /* host wall time of the call */
-  double step_ms;           /* PCG_TIME_KERNELS: summed time of the timed middle steps */
-  int64_t step_launches;    /* PCG_TIME_KERNELS: number of middle-step launches timed */
+  double step_ms;           /* PCG_TIME_KERNELS: summed time of the middle steps of the
+                               applications that did work (one right-hand side, k >= 3) */
+  int64_t step_launches;    /* PCG_TIME_KERNELS: number of middle-step launches in step_ms */
 } pcg_stats;
 
 typedef struct pcheb_handle_s* pcheb_handle;

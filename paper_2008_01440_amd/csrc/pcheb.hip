@@ -1521,9 +1521,11 @@ static pcheb_status solve_impl(Handle& h, const double* b, double* x, int nrhs, 
   pcg_stats local;
   fill_stats(h, hs[worst], flags, &local);
   if (timed && h.prm.k >= 3 && nrhs == 1) {
-    // applications that ran: the initial one plus one per non-final iteration
-    const int64_t applies = local.n_spmv - local.iters;
-    const size_t pairs = std::min(timer.used / 2, size_t(applies / std::max(1, h.prm.k)));
+    // applications that did work: the initial one plus one per non-final iteration (the
+    // final iteration stops before its application, whose launches exit at once; n_spmv
+    // still counts that one when maxit ends the solve, as the unfused loop would run it)
+    const int64_t ran = local.iters >= 1 ? local.iters : (hs[worst].done == kConverged ? 0 : 1);
+    const size_t pairs = std::min(timer.used / 2, size_t(ran));
     double ms = 0.0;
     for (size_t i = 0; i < pairs; ++i) {
       float t = 0.f;
