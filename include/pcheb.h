@@ -73,7 +73,8 @@ typedef enum pcheb_precision {
  * STENCIL7: the 7-point Laplacian on an nx*ny*nz grid, x fastest, with
  *   homogeneous Dirichlet boundaries; n must equal nx*ny*nz.
  * STENCIL27H: cell-centred diffusion on an nx*ny*nz grid, x fastest.
- *   cell_coeff (float64[n], device, borrowed, all > 0) holds the cell
+ *   cell_coeff (float64[n], device, borrowed, all in [1e-150, 1e150], else
+ *   INVALID; a value <= 0 or not finite is NOT_SPD) holds the cell
  *   coefficients k_i.  Cell i couples to each of its 26 neighbours j with
  *   -H(k_i, k_j), H(a, b) = 2ab/(a + b); a neighbour outside the grid adds
  *   k_i to the diagonal (zero-Dirichlet ghost cell).

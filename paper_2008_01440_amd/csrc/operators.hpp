@@ -180,7 +180,11 @@ __device__ __forceinline__ void KStencil7<SCALED, TY, ZC, In, Epi>::run(In in, E
 // per phase and the ring is never shifted.
 // The face weight 2 k_i k_n / (k_i + k_n) is 1 / (rho_i + rho_n): one add and
 // the hardware reciprocal, refined in double by one Newton-Raphson step
-// r <- r + r (1 - x r).  Cells outside the grid read y = 0 and rho = 1 (any
+// r <- r + r (1 - x r).  The float64 recurrence steps take the 26 neighbours in
+// 13 consecutive pairs, y1 / d1 + y2 / d2 = (d2 y1 + d1 y2) / (d1 d2), with one
+// reciprocal per pair: the step follows its vector arithmetic, and this halves
+// the reciprocals (192^3 step 88.4 -> 81.0 us).  Setup admits coefficients in
+// [1e-150, 1e150] only, so d1 d2 stays a normal double.  Cells outside the grid read y = 0 and rho = 1 (any
 // positive value: their weight multiplies y = 0); their Dirichlet ghost
 // contributions are in the stored D^-1 (invd), so
 //   SCALED:  m = y_i - invd_i * sum_n w_in y_n      (D^-1 A_hat y)
@@ -322,6 +326,9 @@ __device__ __forceinline__ void KStencil27h<SCALED, TY, ZC, In, Epi>::run(In in,
           // buffers of the planes below, at and above the point: the last three staged
           const uint32_t bz[3] = {(k - 3u) & 3u, (k - 2u) & 3u, (k - 1u) & 3u};
           const acc ri = rs[bz[1]][ty + 1][tx + 1];
+          // consecutive neighbours in pairs: y1 / d1 + y2 / d2 = (d2 y1 + d1 y2) / (d1 d2)
+          double pd = 0.0, py = 0.0;  // the first neighbour of the pair
+          bool second = false;
 #pragma unroll
           for (int dz = 0; dz < 3; ++dz) {
             const acc(*yq)[W] = ys[bz[dz]];
@@ -332,9 +339,17 @@ __device__ __forceinline__ void KStencil27h<SCALED, TY, ZC, In, Epi>::run(In in,
               for (int dx = 0; dx < 3; ++dx) {
                 if (dz == 1 && dy == 1 && dx == 1) continue;
                 const acc d = ri + rq[ty + dy][tx + dx];
-                double w = __builtin_amdgcn_rcp(d);
-                w = fma(fma(-d, w, 1.0), w, w);
-                off += w * yq[ty + dy][tx + dx];
+                const acc yn = yq[ty + dy][tx + dx];
+                if (second) {
+                  const double dd = pd * d;
+                  double w = __builtin_amdgcn_rcp(dd);
+                  w = fma(fma(-dd, w, 1.0), w, w);
+                  off = fma(w, fma(pd, yn, d * py), off);
+                } else {
+                  pd = d;
+                  py = yn;
+                }
+                second = !second;
               }
             }
           }

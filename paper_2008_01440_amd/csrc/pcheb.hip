@@ -170,7 +170,10 @@ __global__ void k_csr_invdiag(const int32_t* rowptr, const int32_t* col, const d
 }
 
 // 27-point harmonic operator diagonal: sum of the 26 harmonic means, k_i for
-// every neighbour outside the grid.  Flags coefficients <= 0.
+// every neighbour outside the grid.  Flags coefficients <= 0 (bit 1) and
+// positive ones outside [kH27CoeffMin, kH27CoeffMax] (bit 4): the float64
+// products multiply two face sums 1/(2 k_i) + 1/(2 k_n), which must stay normal.
+constexpr double kH27CoeffMin = 1e-150, kH27CoeffMax = 1e150;
 __global__ void k_h27_invdiag(const double* kappa, int nx, int ny, int nz, double* invd, int* bad) {
   const int64_t n = int64_t(nx) * ny * nz;
   GRID_STRIDE(i, n) {
@@ -183,6 +186,7 @@ __global__ void k_h27_invdiag(const double* kappa, int nx, int ny, int nz, doubl
       invd[i] = 0.0;
       continue;
     }
+    if (ki < kH27CoeffMin || ki > kH27CoeffMax) atomicOr(bad, 4);
     double d = 0.0;
     for (int dz = -1; dz <= 1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
@@ -1119,7 +1123,8 @@ void setup_operator(Handle& h, hipStream_t s) {
   PCHEB_HIP_CHECK(hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   PCHEB_HIP_CHECK(hipStreamSynchronize(s));
   if (bad_host & 2) fail(PCHEB_INVALID, "block_size 3: the three rows of a node must share one column pattern");
-  if (bad_host) fail(PCHEB_NOT_SPD, "operator has a non-positive diagonal entry, coefficient or 3x3 block");
+  if ((bad_host & 5) == 4) fail(PCHEB_INVALID, "27-point cell coefficients must lie in [1e-150, 1e150]");
+  if (bad_host & 1) fail(PCHEB_NOT_SPD, "operator has a non-positive diagonal entry, coefficient or 3x3 block");
 }
 
 // Recurrence scalars and the scaled operator copies.

@@ -428,6 +428,45 @@ def test_ragged_and_degenerate_grids_27(pc, dims, prec):
     assert abs(res_hat - st["relres_true_hat"]) <= 1e-3 * st["relres_true_hat"] + 1e-15
 
 
+def test_h27_coefficient_range(pc):
+    """27-point coefficients: the float64 products take neighbours in pairs and multiply two face
+    sums 1/(2 k_i) + 1/(2 k_n), so setup admits coefficients in [1e-150, 1e150] only.  Outside it
+    setup returns INVALID; a non-positive coefficient is NOT_SPD (and wins over the range).  Inside
+    it, at contrasts of 1e280, the F64 application still matches the oracle."""
+    dims = (9, 7, 6)
+    base = W.harmonic27_kappa(*dims, seed=4)
+
+    def setup_status(kappa):
+        op = pc.Operator.stencil27h(torch.from_numpy(kappa).to(DEV))
+        try:
+            with pc.pcheb_setup(op, 3, 1e-4, 2.0, 1.001, "f64"):
+                return "OK", ""
+        except pc.PchebError as e:
+            return e.name, str(e)
+
+    for bad in (1e151, 1e-151, 1e300):
+        k = base.copy()
+        k.reshape(-1)[17] = bad
+        name, msg = setup_status(k)
+        assert name == "INVALID" and "1e-150" in msg, (bad, name, msg)
+    k = base.copy()
+    k.reshape(-1)[3], k.reshape(-1)[40] = 1e200, -1.0
+    assert setup_status(k)[0] == "NOT_SPD"
+    k = base.copy()
+    k.reshape(-1)[::7] = 1e140
+    k.reshape(-1)[3::11] = 1e-140
+    rp, ci, v = W.harmonic27_csr(k)
+    n = len(rp) - 1
+    xin = W.uniform(22, n, -1.0, 1.0)
+    ref = oracle.nc_apply_unscaled(rp, ci, v, xin, 1e-4, 2.0, 6, 1.001)
+    with pc.pcheb_setup(pc.Operator.stencil27h(torch.from_numpy(k).to(DEV)), 6, 1e-4, 2.0, 1.001, "f64") as h:
+        z = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_apply(h, _t(xin), z)
+        torch.cuda.synchronize()
+    assert np.isfinite(z.cpu().numpy()).all()
+    assert rel_inf(z.cpu().numpy(), ref) <= APPLY_TOL["f64"]
+
+
 @pytest.mark.parametrize("max_off", [13, 29])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_csr_wide_rows_of_mixed_length(pc, max_off, prec):
