@@ -146,7 +146,9 @@ typedef struct pcg_stats {
   double relres;            /* recursive residual of the scaled system at exit */
   double relres_true;       /* ||b - A x|| / ||b|| of the scaled system, recomputed at exit */
   double relres_true_hat;   /* ||b_hat - A_hat x_hat|| / ||b_hat||, unscaled */
-  int64_t n_spmv;           /* operator products, preconditioner included */
+  int64_t n_spmv;           /* operator products, preconditioner included, counted as the
+                               textbook loop runs them (a solve that maxit ends counts the
+                               application of its last iteration, which the device skips) */
   int64_t n_dot;            /* scalar products, counted as in Table 3 of the paper */
   double seconds;           /* host wall time of the call */
   double step_ms;           /* PCG_TIME_KERNELS: summed time of the middle steps of the
