@@ -346,17 +346,22 @@ __device__ __forceinline__ void KFusedPass64<S, TY, NT>::run(const double* __res
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
   };
   // Level l (2 .. S + 1) is needed only on region rows l - 1 .. RY - l: the rows
-  // beyond are read by no point of level l + 1.  act[l - 2][m] marks owned
-  // point m inside them; wavefronts whose points all lie outside skip the level
-  // (its arithmetic, LDS writes and neighbour reads), and the values they leave
-  // stale are never read.
+  // beyond are read by no point of level l + 1.  act[l - 2][m] is set when some
+  // lane of the wavefront has its point m inside them (a wave-uniform test, so a
+  // scalar branch): wavefronts whose points all lie outside skip the level (its
+  // arithmetic, LDS writes and neighbour reads), and the others compute it at all
+  // their points.  The values at points outside the rows, stale or computed from
+  // stale inputs, are never read, and their global stores fall on out-of-range
+  // offsets.  (A per-lane mask cost more in exec-mask instructions than it saved:
+  // 159.5-160.0 against 157.6-158.3 us.)
   bool act[S][P];
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     const int p = tid + NT * m;
     const int ry = p / RX;
 #pragma unroll
-    for (int l = 2; l <= S + 1; ++l) act[l - 2][m] = p < NP && ry >= l - 1 && ry <= RY - l;
+    for (int l = 2; l <= S + 1; ++l)
+      act[l - 2][m] = __builtin_amdgcn_ballot_w64(p < NP && ry >= l - 1 && ry <= RY - l) != 0;
   }
   XcdTiles tiles(ntiles);
   for (uint32_t t = tiles.begin; t < tiles.end; t += tiles.step) {
