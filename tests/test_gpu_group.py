@@ -263,6 +263,23 @@ def test_group_mixed_outcomes_and_graph_recapture(pc):
         assert torch.equal(X[0, :n], x)
 
 
+def test_group_graph_replays_new_vectors_and_tolerances(pc):
+    """The group's iteration graph holds only table addresses: later calls with other vectors,
+    tolerances and right-hand sides upload new argument packs and replay the same graph.  Every
+    call's solutions equal the single solves bit for bit."""
+    cases = family("st7", 3)
+    n = cases[0].n
+    with Handles(pc, cases, 6, "f32", 4) as hs, pc.pcheb_group_create(hs) as g:
+        for call, (seed, tol) in enumerate([(300, 1e-8), (400, 1e-6), (500, 1e-10), (300, 1e-8)]):
+            B = _rhs(cases, seed)
+            X = torch.full_like(B, float("nan"))  # a new block each call: new vector addresses
+            sts = pc.pcg_solve_group(g, B[:, :n], X[:, :n], tol=tol, flexible=True)
+            Xs, singles = _singles(pc, hs, B, n, tol=tol, flexible=True)
+            for i in range(len(cases)):
+                assert torch.equal(X[i, :n], Xs[i]), (call, i)
+                assert sts[i]["iters"] == singles[i]["iters"] and sts[i]["status"] == "OK", (call, i)
+
+
 def test_group_of_300_small_problems(pc):
     """300 problems in one group (grid dimension z = 300; the state gather spans two blocks):
     7-point 9 x 7 x 5 grids whose bounds differ, so every problem has its own recurrence
