@@ -664,3 +664,67 @@ def test_batched_six_rhs_partial_slot_groups(pc, name, prec):
             assert torch.equal(Y[j, :n], y), (name, prec, j)
     assert stb["status"] == "OK"
     assert float(X[2, :n].abs().max()) == 0.0
+
+
+def _wide_short_rows_csr(n, seed):
+    """A symmetric, diagonally dominant CSR matrix with n >= 2^20 rows of about three nonzeros
+    (tridiagonal), some up to seven (extra couplings at distances 2..4), 64 rows of about 24 (past
+    the eight pair slots of four lanes), and a last row holding only its diagonal, so the last entry
+    of the arrays is a row's first slot."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n - 2)  # couplings (i, i + 1), leaving row n - 1 alone
+    rows, cols = [i], [i + 1]
+    for dist in (2, 3, 4):
+        j = rng.choice(n - 1 - dist, size=n // 50, replace=False)
+        rows.append(j)
+        cols.append(j + dist)
+    hubs = rng.choice(n - 20, size=64, replace=False)  # rows of about 24 nonzeros
+    for dist in range(5, 15):
+        rows.append(hubs)
+        cols.append(hubs + dist)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    w = -rng.uniform(0.5, 1.5, size=r.size)
+    import scipy.sparse as sp
+    off = sp.coo_matrix((w, (r, c)), shape=(n, n)).tocsr()
+    off = off + off.T
+    diag = 1.0 + np.asarray(abs(off).sum(axis=1)).ravel() + rng.uniform(0.0, 0.5, size=n)
+    a = (off + sp.diags(diag)).tocsr()
+    a.sort_indices()
+    return a.indptr.astype(np.int32), a.indices.astype(np.int32), a.data.astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_csr_wide_short_rows(pc, prec):
+    """Large CSR matrices with short rows take four lanes per row and read each lane's two
+    nonzeros as one pair (wide launches from 2^20 rows): the product, an application and a batch
+    of three right-hand sides against the oracle and against single applications, on a ragged row
+    count, rows longer than the pair slots, and a last row whose only entry ends the arrays."""
+    n = (1 << 20) + 37
+    rp, ci, v = _wide_short_rows_csr(n, 7)
+    assert rp[-2] == rp[-1] - 1 and ci[-1] == n - 1  # the last row holds only its diagonal
+    assert 2.5 < len(ci) / n <= 10.0 and np.diff(rp).max() > 8
+    lo, hi, k = 1e-3, 2.0, 4
+    d = tuple(_t(a) for a in (rp, ci, v))
+    ld = n + (n % 2)
+    R = torch.zeros((3, ld), dtype=torch.float64, device=DEV)
+    for j in range(3):
+        R[j, :n] = _t(W.uniform(300 + j, n, -1.0, 1.0))
+    R = R[:, :n]
+    with pc.pcheb_setup(pc.Operator.csr(*d), k, lo, hi, 1.001, prec) as h:
+        y = torch.empty(n, dtype=torch.float64, device=DEV)
+        pc.pcheb_matvec(h, R[0].contiguous(), y)
+        Z = torch.empty((3, ld), dtype=torch.float64, device=DEV)[:, :n]
+        pc.pcheb_apply(h, R, Z)
+        singles = []
+        for j in range(3):
+            z = torch.empty(n, dtype=torch.float64, device=DEV)
+            pc.pcheb_apply(h, R[j].contiguous(), z)
+            singles.append(z)
+        torch.cuda.synchronize()
+    r0 = R[0].cpu().numpy()
+    assert rel_inf(y.cpu().numpy(), oracle.csr(rp, ci, v) @ r0) <= 1e-13
+    ref = oracle.nc_apply_unscaled(rp, ci, v, r0, lo, hi, k, 1.001)
+    assert rel_inf(singles[0].cpu().numpy(), ref) <= APPLY_TOL[prec]
+    for j in range(3):
+        assert torch.equal(Z[j], singles[j]), j
